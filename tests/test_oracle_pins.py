@@ -1,0 +1,453 @@
+"""Pins of the CPU oracle to mathematics it does not compute itself.
+
+Each test checks the oracle against something independent of its own
+arithmetic: closed forms, library routines (scipy), brute-force summation
+over ancestral states, invariants of the model, or exact combinatorics.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy.linalg import expm
+from scipy.special import gammainc, gammaincinv
+
+import synth
+from oracle import core as oc
+from oracle import topo
+from tests import bruteforce
+
+PAIRS = [(0, 1), (0, 2), (0, 3), (1, 2), (1, 3), (2, 3)]
+
+
+def scipy_gamma_rates(alpha, K):
+    """Category means of Gamma(alpha, rate alpha) over K equal quantiles."""
+    cuts = [gammaincinv(alpha, i / K) for i in range(1, K)]
+    cum = [0.0] + [gammainc(alpha + 1.0, y) for y in cuts] + [1.0]
+    return np.array([K * (cum[i + 1] - cum[i]) for i in range(K)])
+
+
+def rand_model(seed):
+    rng = np.random.default_rng(seed)
+    return synth.gtr_params(rng)
+
+
+# ----------------------------------------------------------------- model
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_rate_matrix_invariants(seed):
+    rates, freqs = rand_model(seed)
+    Q = oc.rate_matrix(rates, freqs)
+    assert np.allclose(Q.sum(axis=1), 0.0, atol=1e-15)
+    # time reversibility
+    D = np.diag(freqs)
+    assert np.allclose(D @ Q, (D @ Q).T, atol=1e-15)
+    # one expected substitution per unit time
+    assert abs(-np.dot(freqs, np.diag(Q)) - 1.0) < 1e-14
+    # off-diagonals proportional to exchangeability times target frequency
+    ratios = [Q[i, j] / (r * freqs[j]) for r, (i, j) in zip(rates, PAIRS)]
+    ratios += [Q[j, i] / (r * freqs[i]) for r, (i, j) in zip(rates, PAIRS)]
+    assert np.ptp(ratios) < 1e-13 * np.mean(ratios)
+
+
+@pytest.mark.parametrize("t", [0.0, 1e-8, 0.01, 0.3, 2.0, 40.0])
+def test_pmatrix_jc_closed_form(t):
+    Q = oc.rate_matrix(np.ones(6), np.full(4, 0.25))
+    P, _, _ = oc.pmatrix(Q, t)
+    e = math.exp(-4.0 * t / 3.0)
+    want = np.full((4, 4), 0.25 - 0.25 * e)
+    np.fill_diagonal(want, 0.25 + 0.75 * e)
+    assert np.max(np.abs(P - want)) < 1e-14
+
+
+@pytest.mark.parametrize("seed", [3, 4])
+@pytest.mark.parametrize("t", [1e-6, 0.05, 0.7, 5.0, 100.0])
+def test_pmatrix_vs_scipy(seed, t):
+    rates, freqs = rand_model(seed)
+    Q = oc.rate_matrix(rates, freqs)
+    P, dP, d2P = oc.pmatrix(Q, t)
+    ref = expm(Q * t)
+    assert np.max(np.abs(P - ref)) < 1e-13
+    assert np.allclose(P.sum(axis=1), 1.0, atol=1e-13)
+    # derivatives against central differences of scipy's exponential
+    h = 1e-5
+    fd1 = (expm(Q * (t + h)) - expm(Q * (t - h))) / (2 * h)
+    assert np.max(np.abs(dP - fd1)) < 1e-8
+    h = 1e-3   # second differences: roundoff ~ eps/h^2, truncation ~ h^2
+    fd2 = (expm(Q * (t + h)) - 2 * ref + expm(Q * (t - h))) / (h * h)
+    assert np.max(np.abs(d2P - fd2)) < 1e-5
+
+
+def test_chapman_kolmogorov():
+    rates, freqs = rand_model(5)
+    Q = oc.rate_matrix(rates, freqs)
+    a, _, _ = oc.pmatrix(Q, 0.13)
+    b, _, _ = oc.pmatrix(Q, 0.29)
+    c, _, _ = oc.pmatrix(Q, 0.42)
+    assert np.max(np.abs(a @ b - c)) < 1e-14
+
+
+@pytest.mark.parametrize("a", [0.1, 0.5, 1.0, 3.0, 20.0])
+@pytest.mark.parametrize("x", [1e-3, 0.3, 1.0, 4.0, 30.0])
+def test_incomplete_gamma_vs_scipy(a, x):
+    assert abs(oc.gammp(a, x) - gammainc(a, x)) < 1e-13
+
+
+@pytest.mark.parametrize("alpha", [0.05, 0.5, 1.0, 2.7, 50.0])
+@pytest.mark.parametrize("K", [2, 4, 8])
+def test_gamma_rates_vs_scipy(alpha, K):
+    r = oc.gamma_rates(alpha, K)
+    assert np.max(np.abs(r - scipy_gamma_rates(alpha, K))) < 1e-10
+    assert abs(r.mean() - 1.0) < 1e-12
+    assert np.all(np.diff(r) > 0)
+
+
+def test_gamma_rates_limits():
+    assert oc.gamma_rates(0.5, 1)[0] == 1.0
+    assert np.max(np.abs(oc.gamma_rates(1e6, 4) - 1.0)) < 2e-3
+
+
+# ------------------------------------------------------------ likelihood
+
+def small_case(n, seed, K=4, sites=60, jc=False, mean=0.15):
+    rng = np.random.default_rng(seed)
+    edges, brlen = synth.random_tree(n, rng, mean=mean)
+    aln = synth.make_alignment(edges, brlen, n, sites, rng, alpha=0.7, n_cats=K, jc=jc)
+    return edges, brlen, aln
+
+
+def brute(edges, brlen, aln):
+    Q = oc.rate_matrix(aln.rates, aln.freqs)
+    cats = scipy_gamma_rates(aln.alpha, aln.n_cats) if aln.n_cats > 1 else [1.0]
+    return bruteforce.loglik(edges, brlen, aln.tips, aln.weights, Q, aln.freqs, cats)
+
+
+@pytest.mark.parametrize("n,seed,K,jc", [(2, 1, 1, True), (2, 2, 4, False), (3, 3, 4, False),
+                                          (4, 4, 1, False), (4, 5, 4, False), (5, 6, 4, False),
+                                          (5, 7, 1, True)])
+def test_pruning_vs_bruteforce(n, seed, K, jc):
+    edges, brlen, aln = small_case(n, seed, K=K, jc=jc)
+    want = brute(edges, brlen, aln)
+    got = oc.loglik(oc.Data.from_alignment(aln), edges, brlen)
+    assert abs(got - want) <= 1e-12 * abs(want)
+
+
+def test_bruteforce_ambiguous_codes():
+    edges, brlen, aln = small_case(5, 8, K=2)
+    tips = aln.tips.copy()
+    tips[1, ::3] = 15          # gap / N
+    tips[3, 1::4] = 1 | 4      # purine
+    aln.tips = tips
+    want = brute(edges, brlen, aln)
+    got = oc.loglik(oc.Data.from_alignment(aln), edges, brlen)
+    assert abs(got - want) <= 1e-12 * abs(want)
+
+
+def test_config_c1_bruteforce_all_topologies():
+    """5 taxa x 200 sites, JC69, every one of the 15 topologies."""
+    rng = np.random.default_rng(1)
+    edges, brlen = synth.random_tree(5, rng, mean=0.1)
+    aln = synth.make_alignment(edges, brlen, 5, 200, rng, n_cats=1, jc=True)
+    D = oc.Data.from_alignment(aln)
+    for top in synth.all_topologies(5):
+        bl = rng.exponential(0.1, size=7)
+        want = brute(top, bl, aln)
+        assert abs(oc.loglik(D, top, bl) - want) <= 1e-12 * abs(want)
+
+
+def test_pulley_principle():
+    rng = np.random.default_rng(11)
+    edges, brlen = synth.yule_tree(12, rng, mean=0.1)
+    aln = synth.make_alignment(edges, brlen, 12, 300, rng)
+    D = oc.Data.from_alignment(aln)
+    vals = [oc.loglik(D, edges, brlen, at_edge=e) for e in range(len(edges))]
+    vals += [oc.loglik_node(D, edges, brlen, root=v) for v in range(12, 22)]
+    assert np.ptp(vals) <= 1e-12 * abs(vals[0])
+
+
+def test_long_branch_limit():
+    """All lengths huge: leaves independent, L_p = prod_leaves pi_x."""
+    rng = np.random.default_rng(12)
+    edges, _ = synth.random_tree(9, rng)
+    aln = synth.make_alignment(edges, np.full(15, 0.2), 9, 100, rng, n_cats=1)
+    D = oc.Data.from_alignment(aln)
+    got = oc.loglik(D, edges, np.full(15, 800.0))
+    state = np.log2(aln.tips).astype(int)
+    want = float(np.sum(aln.weights * np.log(aln.freqs[state]).sum(axis=0)))
+    assert abs(got - want) <= 1e-12 * abs(want)
+
+
+def test_zero_lengths():
+    rng = np.random.default_rng(13)
+    edges, _ = synth.random_tree(6, rng)
+    tips = np.array([[1, 2, 8, 1]] * 6, dtype=np.uint8)
+    rates, freqs = rand_model(13)
+    D = oc.Data(tips, [1.0, 2.0, 3.0, 1.0], rates, freqs, 0.5, 4)
+    got = oc.loglik(D, edges, np.zeros(9))
+    want = 1.0 * math.log(freqs[0]) + 2 * math.log(freqs[1]) + 3 * math.log(freqs[3]) + math.log(freqs[0])
+    assert abs(got - want) < 1e-12
+    tips2 = tips.copy()
+    tips2[2, 0] = 4
+    D2 = oc.Data(tips2, [1.0, 2.0, 3.0, 1.0], rates, freqs, 0.5, 4)
+    assert oc.loglik(D2, edges, np.zeros(9)) == -math.inf
+
+
+def test_compression_invariance():
+    rng = np.random.default_rng(14)
+    n, S = 10, 400
+    edges, brlen = synth.yule_tree(n, rng, mean=0.1)
+    rates, freqs = synth.gtr_params(rng)
+    states = synth.simulate(edges, brlen, n, rates, freqs, 0.5, S, rng)
+    tips, w = synth.compress(states)
+    assert tips.shape[1] < S and w.sum() == S
+    full = synth.TIP_CODE[states]
+    a = oc.loglik(oc.Data(tips, w, rates, freqs, 0.5, 4), edges, brlen)
+    b = oc.loglik(oc.Data(full, np.ones(S), rates, freqs, 0.5, 4), edges, brlen)
+    assert abs(a - b) <= 1e-12 * abs(b)
+
+
+def test_scaling_exact_when_not_needed():
+    rng = np.random.default_rng(15)
+    edges, brlen = synth.yule_tree(27, rng)
+    aln = synth.make_alignment(edges, brlen, 27, 500, rng)
+    D = oc.Data.from_alignment(aln)
+    assert oc.loglik(D, edges, brlen, scaling=True) == pytest.approx(
+        oc.loglik(D, edges, brlen, scaling=False), rel=1e-13)
+
+
+def test_scaling_rescues_underflow():
+    """600 taxa on huge branches: every L_p is near 0.25^600 ~ 1e-361, below
+    the double range.  With scaling the exact long-branch value comes out."""
+    n = 600
+    rng = np.random.default_rng(16)
+    edges, _ = synth.random_tree(n, rng)
+    E = len(edges)
+    tips = synth.TIP_CODE[rng.integers(0, 4, size=(n, 3))]
+    freqs = np.full(4, 0.25)
+    D = oc.Data(tips, np.ones(3), np.ones(6), freqs, 1.0, 1)
+    want = 3 * n * math.log(0.25)
+    got = oc.loglik(D, edges, np.full(E, 200.0), scaling=True)
+    assert abs(got - want) <= 1e-11 * abs(want)
+    assert oc.loglik(D, edges, np.full(E, 200.0), scaling=False) == -math.inf
+
+
+# ------------------------------------------------------------ derivatives
+
+def test_edge_derivatives_vs_central_differences():
+    rng = np.random.default_rng(17)
+    edges, brlen = synth.yule_tree(9, rng, mean=0.1)
+    aln = synth.make_alignment(edges, brlen, 9, 300, rng)
+    D = oc.Data.from_alignment(aln)
+    h = 1e-5
+    for e in range(len(edges)):
+        l0, d1, d2 = oc.edge_derivs(D, edges, brlen, e)
+        bp, bm = brlen.copy(), brlen.copy()
+        bp[e] += h
+        bm[e] -= h
+        lp, lm = oc.loglik(D, edges, bp), oc.loglik(D, edges, bm)
+        fd1 = (lp - lm) / (2 * h)
+        fd2 = (lp - 2 * l0 + lm) / (h * h)
+        assert abs(d1 - fd1) <= 1e-6 * max(1.0, abs(d1))
+        _, d1p, _ = oc.edge_derivs(D, edges, bp, e)
+        _, d1m, _ = oc.edge_derivs(D, edges, bm, e)
+        assert abs(d2 - (d1p - d1m) / (2 * h)) <= 1e-5 * max(1.0, abs(d2))
+        assert abs(d2 - fd2) <= 2e-2 * max(1.0, abs(d2))
+
+
+def test_gradient_all_edges():
+    rng = np.random.default_rng(18)
+    edges, brlen = synth.yule_tree(8, rng, mean=0.1)
+    aln = synth.make_alignment(edges, brlen, 8, 200, rng)
+    D = oc.Data.from_alignment(aln)
+    l, g, hd = oc.gradient(D, edges, brlen)
+    assert l == pytest.approx(oc.loglik(D, edges, brlen), rel=1e-14)
+    for e in range(len(edges)):
+        _, d1, d2 = oc.edge_derivs(D, edges, brlen, e)
+        assert g[e] == d1 and hd[e] == d2
+
+
+# ------------------------------------------------------------ optimiser
+
+def jc_two_taxon(N, k):
+    """Closed-form ML length and lnL for two JC69 sequences, k mismatches."""
+    p = k / N
+    x = 1.0 - 4.0 * p / 3.0
+    t = -0.75 * math.log(x)
+    lnl = N * math.log(0.25) + (N - k) * math.log(0.25 + 0.75 * x) + k * math.log(0.25 - 0.25 * x)
+    return t, lnl
+
+
+def two_taxon_data(N, k):
+    tips = np.array([[1] * N, [1] * (N - k) + [2] * k], dtype=np.uint8)
+    return oc.Data(tips, np.ones(N), np.ones(6), np.full(4, 0.25), 1.0, 1)
+
+
+@pytest.mark.parametrize("N,k", [(200, 37), (200, 1), (1000, 300), (50, 20)])
+def test_two_taxon_closed_form(N, k):
+    t_hat, l_hat = jc_two_taxon(N, k)
+    for start in (1e-4, 0.1, 5.0):
+        l, b, _, conv = oc.optimize(two_taxon_data(N, k), [[0, 1]], [start])
+        assert conv
+        assert abs(b[0] - t_hat) < 1e-9
+        assert abs(l - l_hat) < 1e-9
+
+
+def test_two_taxon_example_value():
+    """N = 200 sites with 37 differences."""
+    t_hat, l_hat = jc_two_taxon(200, 37)
+    assert t_hat == pytest.approx(0.21243560653793642, abs=1e-15)
+    assert l_hat == pytest.approx(-413.68575471496695, abs=1e-10)
+
+
+def test_two_taxon_boundaries():
+    # no differences: the optimum is the lower bound, where each site has
+    # probability (1/4) P_ii(t_min)
+    l, b, _, _ = oc.optimize(two_taxon_data(100, 0), [[0, 1]], [0.3])
+    assert abs(b[0] - oc.T_MIN) < 1e-15
+    pii = 0.25 + 0.75 * math.exp(-4.0 * oc.T_MIN / 3.0)
+    assert abs(l - 100 * math.log(0.25 * pii)) < 1e-9
+    # p >= 3/4: the likelihood increases towards t = infinity, where every
+    # site has probability 1/16; lnL is flat to machine precision far below t_max
+    l, b, _, _ = oc.optimize(two_taxon_data(100, 80), [[0, 1]], [0.3])
+    assert b[0] > 20.0
+    assert abs(l - 100 * math.log(1.0 / 16.0)) < 1e-9
+
+
+def _kkt(D, edges, b):
+    for e in range(len(edges)):
+        _, d1, d2 = oc.edge_derivs(D, edges, b, e)
+        if b[e] <= oc.T_MIN:
+            assert d1 <= 1e-6
+        else:
+            assert abs(d1) <= 1e-5
+            assert d2 < 0
+
+
+@pytest.mark.parametrize("n,seed", [(4, 20), (5, 21), (8, 22)])
+def test_optimum_kkt_and_local_max(n, seed):
+    edges, brlen, aln = small_case(n, seed, sites=300, mean=0.1)
+    D = oc.Data.from_alignment(aln)
+    l, b, _, conv = oc.optimize(D, edges, brlen)
+    assert conv
+    _kkt(D, edges, b)
+    rng = np.random.default_rng(seed)
+    for _ in range(20):
+        pert = np.maximum(b * np.exp(rng.normal(0, 0.01, size=len(b))), oc.T_MIN)
+        assert oc.loglik(D, edges, pert) <= l + 1e-9
+
+
+def _golden_section_ascent(D, edges, b, sweeps=60):
+    """Independent optimiser: 1-D golden-section search per edge on log t."""
+    b = b.copy()
+    g = (math.sqrt(5) - 1) / 2
+    for _ in range(sweeps):
+        for e in range(len(b)):
+            def f(x):
+                bb = b.copy()
+                bb[e] = math.exp(x)
+                return oc.loglik(D, edges, bb)
+            lo, hi = math.log(oc.T_MIN), math.log(5.0)
+            c, d = hi - g * (hi - lo), lo + g * (hi - lo)
+            fc, fd = f(c), f(d)
+            for _ in range(80):
+                if fc > fd:
+                    hi, d, fd = d, c, fc
+                    c = hi - g * (hi - lo)
+                    fc = f(c)
+                else:
+                    lo, c, fc = c, d, fd
+                    d = lo + g * (hi - lo)
+                    fd = f(d)
+            b[e] = math.exp(0.5 * (lo + hi))
+    return oc.loglik(D, edges, b), b
+
+
+def test_optimum_vs_golden_section():
+    edges, brlen, aln = small_case(5, 23, K=4, sites=200, mean=0.1)
+    D = oc.Data.from_alignment(aln)
+    l, b, _, _ = oc.optimize(D, edges, brlen)
+    lg, bg = _golden_section_ascent(D, edges, brlen, sweeps=25)
+    assert abs(l - lg) < 1e-6
+    assert np.max(np.abs(b - bg) / np.maximum(b, 1e-3)) < 1e-3
+
+
+def test_mask_only_moves_masked_edges():
+    edges, brlen, aln = small_case(7, 24, sites=200)
+    D = oc.Data.from_alignment(aln)
+    mask = np.zeros(11, np.uint8)
+    mask[[2, 5]] = 1
+    _, b, _, _ = oc.optimize(D, edges, brlen, mask=mask)
+    keep = mask == 0
+    assert np.array_equal(b[keep], np.maximum(brlen[keep], oc.T_MIN))
+    for e in (2, 5):
+        _, d1, _ = oc.edge_derivs(D, edges, b, e)
+        assert abs(d1) < 1e-5 or b[e] == oc.T_MIN
+
+
+# ------------------------------------------------------------ topology
+
+@pytest.mark.parametrize("n", [4, 5, 6, 7, 8])
+def test_topology_counts(n):
+    tops = topo.all_topologies(n)
+    assert len(tops) == topo.double_factorial_count(n) == [3, 15, 105, 945, 10395][n - 4]
+    assert len({topo.key(t, n) for t in tops}) == len(tops)
+    assert {topo.key(t, n) for t in synth.all_topologies(n)} == {topo.key(t, n) for t in tops}
+
+
+@pytest.mark.parametrize("n,seed", [(4, 1), (6, 2), (9, 3), (27, 4), (64, 5)])
+def test_nni_neighbours(n, seed):
+    rng = np.random.default_rng(seed)
+    edges, brlen = synth.random_tree(n, rng)
+    k0 = topo.key(edges, n)
+    nb = topo.nni_neighbors(edges, brlen, n)
+    keys = [topo.key(e, n) for e, _ in nb]
+    assert len(nb) == 2 * (n - 3) == len(set(keys))
+    assert k0 not in keys
+    # each neighbour differs from the parent by exactly one split
+    for k in keys:
+        assert len(set(k) ^ set(k0)) == 2
+    # symmetry: the parent is a neighbour of each neighbour
+    for e, _ in nb[:6]:
+        assert k0 in {topo.key(x, n) for x, _ in topo.nni_neighbors(e, brlen, n)}
+    # lengths stay with their splits; the new central split takes the old central length
+    old = topo.lengths_by_split(edges, brlen, n)
+    for e, b in nb:
+        new = topo.lengths_by_split(e, b, n)
+        assert len(set(new) - set(old)) == 1
+        assert sorted(new.values()) == sorted(old.values())
+    # the generator's own NNI walk reaches the same neighbour set
+    gen = {topo.key(e, n) for e, _ in synth.nni_bfs(edges, brlen, n, 2 * (n - 3))}
+    assert gen == set(keys)
+
+
+def test_key_invariance():
+    rng = np.random.default_rng(30)
+    n = 12
+    edges, _ = synth.random_tree(n, rng)
+    k = topo.key(edges, n)
+    perm = np.arange(2 * n - 2)
+    perm[n:] = n + rng.permutation(n - 2)
+    relabelled = perm[edges]
+    shuffled = relabelled[rng.permutation(len(edges))]
+    flipped = shuffled.copy()
+    flipped[::2] = flipped[::2, ::-1]
+    assert topo.key(flipped, n) == k
+
+
+def test_nni_graph_n5():
+    tops = topo.all_topologies(5)
+    keys = {topo.key(t, 5): t for t in tops}
+    degree = {}
+    for k, t in keys.items():
+        nb = {topo.key(e, 5) for e, _ in topo.nni_neighbors(t, np.ones(7), 5)}
+        assert nb <= set(keys)
+        degree[k] = len(nb)
+    assert set(degree.values()) == {4}
+    # connected
+    seen, stack = set(), [next(iter(keys))]
+    while stack:
+        k = stack.pop()
+        if k in seen:
+            continue
+        seen.add(k)
+        stack += [topo.key(e, 5) for e, _ in topo.nni_neighbors(keys[k], np.ones(7), 5)]
+    assert len(seen) == 15
