@@ -1,0 +1,217 @@
+/*
+ * pt.h -- C ABI of the MI355X tree-likelihood library.
+ *
+ * The library evaluates and maximises the log-likelihood of many unrooted
+ * binary trees ("topologies") over nucleotide alignments under GTR + discrete
+ * Gamma rate variation.  It is the numerical hot path of a systematic search
+ * of the high-likelihood set of topologies: a visited topology has its branch
+ * lengths optimised to maximise the likelihood, and the neighbours proposed by
+ * nearest-neighbour interchange (NNI) are scored by full or partial branch
+ * optimisation (Whidden et al., Methods, "Methods Overview" and "Phylogenetic
+ * Topographer", the enumerated visit steps and the radius option).
+ *
+ * Conventions used by every call:
+ *   - Status codes only; nothing throws across this boundary.  On error the
+ *     outputs are left untouched and pt_last_error() describes the failure.
+ *     Every argument is validated on the host before any device work.
+ *   - States A,C,G,T.  A tip code is a 4-bit mask, bit j set when state j is
+ *     possible (one-hot for a resolved base, 0xF for a gap or N).
+ *   - A tree on n taxa is an edge list int32[2n-3][2] of node ids: leaves are
+ *     0..n-1 (alignment rows), internal nodes n..2n-3 of degree 3.  Edge order
+ *     and orientation are free.  n = 2 is the single edge (0,1).  Branch
+ *     lengths, gradients and masks are indexed like the edges.
+ *   - Host pointers are owned by the caller and only read (or written, for
+ *     outputs) during the call; host-pointer calls are synchronous.  Device
+ *     pointers (the pt_plan_* calls) must stay valid until the work enqueued
+ *     on the given stream has finished.
+ *   - precision PT_FP64: partials stored and combined in FP64.
+ *     precision PT_FP32: partials stored in FP32 with per-pattern power-of-two
+ *     scaling; transition matrices, arithmetic and every sum over patterns in
+ *     FP64.
+ */
+#ifndef PT_H
+#define PT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t pt_status;
+#define PT_OK 0
+#define PT_EINVAL (-1)        /* an argument failed validation */
+#define PT_ENOMEM (-2)        /* host or device allocation failed, or the arena cap */
+#define PT_EDEVICE (-3)       /* a HIP runtime call failed */
+#define PT_EUNSUPPORTED (-4)  /* valid input beyond this build's limits */
+#define PT_EINTERNAL (-5)
+
+#define PT_FP64 0
+#define PT_FP32 1
+
+/* Message of the last failing call on this thread ("" when none). */
+const char *pt_last_error(void);
+
+/* ----------------------------------------------------------------- context */
+
+/* A context owns one device's stream, memory and tuning table.  Limits:
+ * device index as seen by HIP.  The environment variable PT_ARENA_CAP_BYTES
+ * (decimal) caps the device bytes one batch may use; host-pointer batch calls
+ * split a batch that exceeds it into smaller batches with identical results. */
+typedef struct pt_ctx pt_ctx;
+pt_status pt_ctx_create(int32_t device, pt_ctx **out);
+void pt_ctx_destroy(pt_ctx *ctx);
+
+/* ------------------------------------------------------------------- model */
+
+/* GTR + discrete Gamma (the paper's runs use JC69 + Gamma and it supports
+ * GTR; Methods, "Phylogenetic Topographer").  Q_ij = rates_ij * freqs_j for
+ * i != j, normalised to one expected substitution per unit branch length.
+ * n_cats equal-weight categories, each rate the mean of Gamma(alpha, alpha)
+ * over its quantile interval; n_cats = 1 means no rate variation. */
+typedef struct {
+    double rates[6];   /* exchangeabilities AC,AG,AT,CG,CT,GT; > 0, any scale */
+    double freqs[4];   /* A,C,G,T; > 0 and summing to 1 within 1e-9 */
+    double alpha;      /* Gamma shape > 0; ignored when n_cats == 1 */
+    int32_t n_cats;    /* 1..8 */
+} pt_model;
+
+/* An alignment as site patterns: tips uint8[n_taxa][n_patterns] tip codes
+ * (row-major), weights double[n_patterns] (> 0, the pattern counts).  Copied
+ * to the device; the caller's arrays may be freed on return.  2 <= n_taxa,
+ * 1 <= n_patterns. */
+typedef struct pt_aln pt_aln;
+pt_status pt_aln_create(pt_ctx *ctx, int32_t n_taxa, int32_t n_patterns,
+                        const uint8_t *tips, const double *weights,
+                        const pt_model *model, pt_aln **out);
+void pt_aln_destroy(pt_aln *aln);
+
+/* A batch of trees.  Tree b uses alignment alns[aln_index[b]], has n_b taxa
+ * (that alignment's row count) and its 2n_b-3 edges are
+ * edges[2*edge_offset[b] .. 2*edge_offset[b+1]).  Flat per-edge arrays
+ * (lengths, masks, gradients) use the same offsets. */
+typedef struct {
+    int32_t n_trees;
+    const int32_t *aln_index;    /* [n_trees] */
+    const int64_t *edge_offset;  /* [n_trees + 1], edge_offset[0] = 0 */
+    const int32_t *edges;        /* [edge_offset[n_trees]][2] */
+} pt_trees;
+
+/* Branch-length optimisation settings.  Per edge: safeguarded Newton on
+ * t in [t_min, t_max], at most max_newton derivative evaluations, stopping
+ * when a step would move t by at most tol_newton * max(t, 1e-6).  Per tree:
+ * passes over the masked edges until a pass raises lnL by less than tol_lnl
+ * and changes no length by more than tol_t relative, or max_passes. */
+typedef struct {
+    double t_min, t_max;
+    double tol_lnl, tol_t, tol_newton;
+    int32_t max_passes, max_newton;
+} pt_opt;
+
+/* Defaults for a precision (t_min 1e-8, t_max 100). */
+void pt_opt_default(int32_t precision, pt_opt *out);
+
+/* --------------------------------------------------- host-pointer batches */
+
+/* lnL of every tree at the given lengths (brlen[total edges], >= 0). */
+pt_status pt_batch_loglik(pt_ctx *ctx, pt_aln *const *alns, int32_t n_alns,
+                          const pt_trees *trees, const double *brlen,
+                          int32_t precision, double *lnl_out /* [n_trees] */);
+
+/* Maximise lnL over the branch lengths of every tree, starting from
+ * brlen_inout and writing the optimised lengths back.  opt_mask[total edges]
+ * (NULL = all) selects the edges that move (partial optimisation, the
+ * paper's radius option).  opt NULL = pt_opt_default(precision).
+ * passes_out / status_out may be NULL; status 0 = the stopping rule was met,
+ * 1 = max_passes reached first (not an error). */
+pt_status pt_batch_optimize_branches(pt_ctx *ctx, pt_aln *const *alns, int32_t n_alns,
+                                     const pt_trees *trees, double *brlen_inout,
+                                     const uint8_t *opt_mask, const pt_opt *opt,
+                                     int32_t precision, double *lnl_out,
+                                     int32_t *passes_out, int32_t *status_out);
+
+/* lnL and d lnL / d t_e for every edge of every tree (reverse-mode: one
+ * post-order and one pre-order sweep of partials).  hess_diag_out (NULL ok)
+ * receives d2 lnL / d t_e^2. */
+pt_status pt_batch_branch_grad(pt_ctx *ctx, pt_aln *const *alns, int32_t n_alns,
+                               const pt_trees *trees, const double *brlen,
+                               int32_t precision, double *lnl_out,
+                               double *grad_out, double *hess_diag_out);
+
+/* ------------------------------------------------------ device-side plans */
+
+/* A plan compiles a batch once (validation, rooting, the per-tree program of
+ * partial updates and edge steps, device descriptors, partial buffers) so it
+ * can be run many times on device-resident lengths.  kinds is a bitwise OR
+ * of PT_PLAN_*.  opt_mask as in pt_batch_optimize_branches (fixed per plan).
+ * Plan calls enqueue on `stream` (a hipStream_t; NULL = the context's stream)
+ * and return without waiting.  With graphs enabled (pt_plan_set_graphs), each
+ * distinct argument set is captured once into a HIP graph and replayed. */
+#define PT_PLAN_LOGLIK 1
+#define PT_PLAN_OPTIMIZE 2
+#define PT_PLAN_GRAD 4
+typedef struct pt_plan pt_plan;
+pt_status pt_plan_create(pt_ctx *ctx, pt_aln *const *alns, int32_t n_alns,
+                         const pt_trees *trees, const uint8_t *opt_mask,
+                         int32_t precision, int32_t kinds, pt_plan **out);
+void pt_plan_destroy(pt_plan *plan);
+pt_status pt_plan_set_graphs(pt_plan *plan, int32_t enable);
+
+/* d_brlen: device double[total edges]; d_lnl: device double[n_trees]. */
+pt_status pt_plan_loglik(pt_plan *plan, const double *d_brlen, double *d_lnl, void *stream);
+/* d_passes, d_status: device int32[n_trees] or NULL. */
+pt_status pt_plan_optimize(pt_plan *plan, double *d_brlen_inout, const pt_opt *opt,
+                           double *d_lnl, int32_t *d_passes, int32_t *d_status,
+                           void *stream);
+/* d_grad: device double[total edges]; d_hess NULL ok. */
+pt_status pt_plan_grad(pt_plan *plan, const double *d_brlen, double *d_lnl,
+                       double *d_grad, double *d_hess, void *stream);
+
+/* Time the optimisation kernel's launch shapes on this plan (lengths are
+ * restored after every trial) and keep the fastest for the plan and for
+ * every later plan of the same shape class in this context.  Writes the
+ * chosen threads per block and items per thread to *block, *items (NULL ok). */
+pt_status pt_plan_autotune(pt_plan *plan, const double *d_brlen, const pt_opt *opt,
+                           int32_t *block, int32_t *items);
+
+/* Number of trees, total edges and device bytes held by the plan. */
+pt_status pt_plan_info(const pt_plan *plan, int32_t *n_trees, int64_t *n_edges,
+                       int64_t *device_bytes);
+
+/* ----------------------------------------------------- host-only utilities */
+
+/* Validates a model exactly as pt_aln_create does and returns what the
+ * kernels use: cat_rates[n_cats] (category rates, mean 1), and the
+ * eigen-decomposition P(t) = U diag(exp(lam t)) Uinv (U, Uinv row-major 4x4,
+ * lam[4]).  Any output may be NULL.  No device is touched. */
+pt_status pt_model_info(const pt_model *model, double *cat_rates, double *U, double *Uinv,
+                        double *lam);
+
+/* Validates an edge list (node ids in range, leaves of degree 1, internal
+ * nodes of degree 3, connected) without touching a device. */
+pt_status pt_tree_check(int32_t n_taxa, const int32_t *edges);
+
+/* ------------------------------------------------------ host-only topology */
+
+/* The 2(n-3) NNI neighbours (Methods, "Phylogenetic Topographer": the search
+ * visits every NNI neighbour of a queued topology).  For internal edge (u,v)
+ * taken in edge order, with u's other edges a < b and v's other edges c < d
+ * by edge index, neighbour 2i swaps the subtrees on b and c and neighbour
+ * 2i+1 swaps b and d.  Lengths stay with their edges.  Outputs:
+ * out_edges int32[2(n-3)][2n-3][2], out_brlen double[2(n-3)][2n-3] (brlen
+ * may be NULL, then out_brlen is not written), out_touched
+ * int32[2(n-3)][5] (central edge, then b, the swapped partner, and the two
+ * remaining edges at u and v; NULL ok).  n >= 4. */
+pt_status pt_nni_neighbors(int32_t n, const int32_t *edges, const double *brlen,
+                           int32_t *out_edges, double *out_brlen, int32_t *out_touched);
+
+/* Canonical topology key: the n-3 non-trivial splits, each the leaf bitmask
+ * of the side without taxon 0 in W = (n+63)/64 little-endian uint64 words,
+ * sorted ascending (as W-word numbers, most significant word last).
+ * out: uint64[n-3][W].  Equal keys <=> equal unrooted topologies.  n >= 4. */
+pt_status pt_topology_key(int32_t n, const int32_t *edges, uint64_t *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PT_H */

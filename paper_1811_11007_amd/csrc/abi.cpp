@@ -1,0 +1,844 @@
+// abi.cpp -- the C ABI: contexts, alignments, plans and batch entry points.
+//
+// A plan is one compiled batch: every tree validated, its programs emitted
+// (tree.cpp), descriptors and programs uploaded, partial buffers allocated.
+// The host-pointer batch calls build a plan (split to respect the arena cap),
+// run it once and free it; the device-pointer plan calls run it repeatedly,
+// optionally through captured HIP graphs.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+#include "pt_internal.hpp"
+
+using pt::AlnDev;
+using pt::Op;
+using pt::TreeDev;
+
+namespace {
+
+thread_local std::string g_err;
+
+pt_status fail(pt_status st, const std::string &msg) {
+    g_err = msg;
+    return st;
+}
+
+#define PT_HIP(call)                                                                           \
+    do {                                                                                       \
+        hipError_t e_ = (call);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            return fail(e_ == hipErrorOutOfMemory ? PT_ENOMEM : PT_EDEVICE,                     \
+                        std::string(#call) + ": " + hipGetErrorString(e_));                    \
+    } while (0)
+
+// LDS the kernels may use for the per-tree transition matrix cache.
+constexpr size_t kLdsBudget = 64 * 1024;
+constexpr int kMaxOptItems = 1024 * 16;
+
+int64_t arena_cap() {
+    const char *s = std::getenv("PT_ARENA_CAP_BYTES");
+    if (!s || !*s) return -1;
+    char *end = nullptr;
+    long long v = std::strtoll(s, &end, 10);
+    return (end && *end == 0 && v > 0) ? (int64_t)v : -1;
+}
+
+}  // namespace
+
+struct pt_ctx {
+    int device = 0;
+    int n_cu = 0;
+    hipStream_t stream = nullptr;
+    // tuned launch shape per (precision, Kp, item capacity)
+    std::map<std::tuple<int, int, int>, std::pair<int, int>> tuned;
+};
+
+struct pt_aln {
+    pt_ctx *ctx = nullptr;
+    int n_taxa = 0, P = 0;
+    AlnDev desc{};
+    uint8_t *d_tips = nullptr;
+    double *d_w = nullptr;
+};
+
+struct pt_plan {
+    pt_ctx *ctx = nullptr;
+    int precision = 0, kinds = 0;
+    int n_trees = 0;
+    int64_t n_edges = 0;
+    int max_items = 0, max_E = 0, n_tiles = 0, kp = 1;
+    std::vector<int> tree_E;
+    AlnDev *d_alns = nullptr;
+    Op *d_ops = nullptr;
+    TreeDev *d_trees_ll = nullptr, *d_trees_gr = nullptr, *d_trees_opt = nullptr;
+    int32_t *d_tile_tree = nullptr, *d_edge_tree = nullptr, *d_order = nullptr, *d_queue = nullptr;
+    void *d_clv = nullptr;
+    uint16_t *d_cnt = nullptr;
+    double *d_pmat = nullptr, *d_part = nullptr, *d_scratch = nullptr;
+    size_t lds_tiles = 0, lds_opt = 0;
+    int opt_block = 0, opt_items = 0, opt_grid = 0;
+    int64_t device_bytes = 0;
+    bool graphs = false;
+    std::map<std::vector<uint64_t>, hipGraphExec_t> execs;
+    std::vector<void *> allocs;
+};
+
+namespace {
+
+template <typename P>
+pt_status dev_alloc(pt_plan *pl, P **out, size_t bytes) {
+    void *p = nullptr;
+    if (bytes == 0) bytes = 16;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) return fail(PT_ENOMEM, "hipMalloc(" + std::to_string(bytes) + "): " + hipGetErrorString(e));
+    pl->allocs.push_back(p);
+    pl->device_bytes += (int64_t)bytes;
+    *out = reinterpret_cast<P *>(p);
+    return PT_OK;
+}
+
+void free_plan(pt_plan *pl) {
+    if (!pl) return;
+    for (auto &kv : pl->execs) (void)hipGraphExecDestroy(kv.second);
+    for (void *p : pl->allocs) (void)hipFree(p);
+    delete pl;
+}
+
+pt_status check_opt(const pt_opt &o) {
+    if (!(o.t_min > 0.0) || !(o.t_max > o.t_min) || !std::isfinite(o.t_max))
+        return fail(PT_EINVAL, "pt_opt: need 0 < t_min < t_max < inf");
+    if (!(o.tol_lnl >= 0.0) || !(o.tol_t >= 0.0) || !(o.tol_newton >= 0.0))
+        return fail(PT_EINVAL, "pt_opt: tolerances must be >= 0");
+    if (o.max_passes < 1 || o.max_newton < 1) return fail(PT_EINVAL, "pt_opt: max_passes and max_newton must be >= 1");
+    return PT_OK;
+}
+
+pt::OptParams to_params(const pt_opt &o) {
+    pt::OptParams p;
+    p.t_min = o.t_min;
+    p.t_max = o.t_max;
+    p.tol_lnl = o.tol_lnl;
+    p.tol_t = o.tol_t;
+    p.tol_newton = o.tol_newton;
+    p.max_passes = o.max_passes;
+    p.max_newton = o.max_newton;
+    return p;
+}
+
+// Validates the batch description and returns per-tree taxon counts.
+pt_status check_trees(pt_ctx *ctx, pt_aln *const *alns, int32_t n_alns, const pt_trees *trees,
+                      std::vector<int> &n_taxa) {
+    if (!ctx) return fail(PT_EINVAL, "ctx is NULL");
+    if (!trees) return fail(PT_EINVAL, "trees is NULL");
+    if (trees->n_trees < 0) return fail(PT_EINVAL, "n_trees < 0");
+    if (trees->n_trees > 0 && (!trees->aln_index || !trees->edge_offset || !trees->edges))
+        return fail(PT_EINVAL, "trees: NULL array");
+    if (n_alns < 1 || !alns) return fail(PT_EINVAL, "need at least one alignment");
+    for (int i = 0; i < n_alns; ++i) {
+        if (!alns[i]) return fail(PT_EINVAL, "alns[" + std::to_string(i) + "] is NULL");
+        if (alns[i]->ctx != ctx) return fail(PT_EINVAL, "alignment belongs to another context");
+    }
+    if (trees->n_trees > 0 && trees->edge_offset[0] != 0) return fail(PT_EINVAL, "edge_offset[0] must be 0");
+    n_taxa.resize(trees->n_trees);
+    for (int b = 0; b < trees->n_trees; ++b) {
+        int ai = trees->aln_index[b];
+        if (ai < 0 || ai >= n_alns) return fail(PT_EINVAL, "tree " + std::to_string(b) + ": aln_index out of range");
+        int n = alns[ai]->n_taxa;
+        int64_t want = n == 2 ? 1 : 2 * n - 3;
+        if (trees->edge_offset[b + 1] - trees->edge_offset[b] != want)
+            return fail(PT_EINVAL, "tree " + std::to_string(b) + ": edge count must be 2n-3 = " + std::to_string(want));
+        n_taxa[b] = n;
+    }
+    return PT_OK;
+}
+
+pt_status check_lengths(const double *brlen, int64_t n) {
+    if (n > 0 && !brlen) return fail(PT_EINVAL, "brlen is NULL");
+    for (int64_t i = 0; i < n; ++i)
+        if (!(brlen[i] >= 0.0) || !std::isfinite(brlen[i]))
+            return fail(PT_EINVAL, "branch length " + std::to_string(i) + " is negative or not finite");
+    return PT_OK;
+}
+
+size_t store_bytes(int precision) { return precision == PT_FP32 ? 4 : 8; }
+
+// Device bytes a one-tree plan of this shape needs (for the arena cap).
+int64_t tree_bytes(int n, const AlnDev &a, int precision, int kinds) {
+    const int E = n == 2 ? 1 : 2 * n - 3, slots = n >= 3 ? 3 * (n - 2) : 0;
+    const int64_t items = (int64_t)a.P * a.Kp;
+    int64_t b = (int64_t)slots * items * 4 * store_bytes(precision) + (int64_t)slots * a.P * 2;
+    b += (int64_t)E * a.Kp * 16 * 8 + 64 * E + 256;
+    if (kinds & (PT_PLAN_LOGLIK | PT_PLAN_GRAD)) {
+        int64_t tiles = (items + pt::kTileBlock * pt::kTileItems - 1) / (pt::kTileBlock * pt::kTileItems);
+        b += tiles * (int64_t)E * 3 * 8 + tiles * 4;
+    }
+    return b;
+}
+
+void pick_shape(pt_plan *pl) {
+    static const int blocks[3] = {256, 512, 1024};
+    static const int items[6] = {1, 2, 4, 8, 12, 16};
+    int best_b = 0, best_i = 0;
+    long best_cap = 0;
+    for (int ii : items)
+        for (int bb : blocks) {
+            if (!pt::optimize_shape_supported(bb, ii)) continue;
+            long cap = (long)bb * ii;
+            if (cap < pl->max_items) continue;
+            if (!best_b || cap < best_cap || (cap == best_cap && ii < best_i)) {
+                best_b = bb; best_i = ii; best_cap = cap;
+            }
+        }
+    pl->opt_block = best_b;
+    pl->opt_items = best_i;
+}
+
+int kp_of_plan(pt_aln *const *alns, int n_alns) {
+    int kp = 1;
+    for (int i = 0; i < n_alns; ++i) kp = std::max(kp, alns[i]->desc.Kp);
+    return kp;
+}
+
+pt_status plan_build(pt_ctx *ctx, pt_aln *const *alns, int32_t n_alns, const pt_trees *trees,
+                     const uint8_t *mask, int precision, int kinds, pt_plan **out) {
+    if (precision != PT_FP32 && precision != PT_FP64) return fail(PT_EINVAL, "precision must be PT_FP64 or PT_FP32");
+    if (kinds <= 0 || kinds > 7) return fail(PT_EINVAL, "kinds must be a non-empty OR of PT_PLAN_*");
+    std::vector<int> ntx;
+    pt_status st = check_trees(ctx, alns, n_alns, trees, ntx);
+    if (st) return st;
+    const int B = trees->n_trees;
+    const int64_t NE = B ? trees->edge_offset[B] : 0;
+    if (mask)
+        for (int64_t i = 0; i < NE; ++i)
+            if (mask[i] > 1) return fail(PT_EINVAL, "opt_mask entries must be 0 or 1");
+
+    std::unique_ptr<pt_plan, void (*)(pt_plan *)> pl(new pt_plan, free_plan);
+    pl->ctx = ctx;
+    pl->precision = precision;
+    pl->kinds = kinds;
+    pl->n_trees = B;
+    pl->n_edges = NE;
+
+    std::vector<Op> ops;
+    std::vector<TreeDev> tll(B), tgr(B), top(B);
+    std::vector<int32_t> tile_tree, edge_tree(NE);
+    std::vector<double> cost(B);
+    int64_t clv_off = 0, cnt_off = 0, pm_off = 0;
+    int tiles = 0;
+    const int64_t tile_items = (int64_t)pt::kTileBlock * pt::kTileItems;
+    std::string err;
+    for (int b = 0; b < B; ++b) {
+        const pt_aln *al = alns[trees->aln_index[b]];
+        const AlnDev &ad = al->desc;
+        pt::Tree t;
+        const int32_t *ed = trees->edges + 2 * trees->edge_offset[b];
+        st = pt::build_tree(ntx[b], ed, t, err);
+        if (st) return fail(st, "tree " + std::to_string(b) + ": " + err);
+        const int E = t.n_edges;
+        if ((size_t)E * ad.Kp * 16 * 8 + (size_t)E * 8 > kLdsBudget)
+            return fail(PT_EUNSUPPORTED, "tree " + std::to_string(b) + ": (2n-3) * padded categories exceeds the 64 KiB "
+                                         "transition-matrix cache (at most 504 edge-categories)");
+        const int items = ad.P * ad.Kp;
+        if ((kinds & PT_PLAN_OPTIMIZE) && items > kMaxOptItems)
+            return fail(PT_EUNSUPPORTED, "tree " + std::to_string(b) + ": patterns x padded categories exceeds 16384 "
+                                         "for branch optimisation");
+        pl->max_items = std::max(pl->max_items, items);
+        pl->max_E = std::max(pl->max_E, E);
+        pl->tree_E.push_back(E);
+        TreeDev base{};
+        base.aln = trees->aln_index[b];
+        base.n_edges = E;
+        base.n_slots = t.n_slots();
+        base.clv_off = clv_off;
+        base.cnt_off = cnt_off;
+        base.edge_off = trees->edge_offset[b];
+        base.pm_off = pm_off;
+        base.n_tiles = (int)((items + tile_items - 1) / tile_items);
+        base.tile_begin = tiles;
+        clv_off += (int64_t)t.n_slots() * items * 4;
+        cnt_off += (int64_t)t.n_slots() * ad.P;
+        pm_off += (int64_t)E * ad.Kp * 16;
+        for (int64_t i = 0; i < E; ++i) edge_tree[base.edge_off + i] = b;
+        tll[b] = tgr[b] = top[b] = base;
+        if (kinds & (PT_PLAN_LOGLIK | PT_PLAN_GRAD)) {
+            for (int x = 0; x < base.n_tiles; ++x) tile_tree.push_back(b);
+            tiles += base.n_tiles;
+        }
+        if (kinds & PT_PLAN_LOGLIK) {
+            std::vector<Op> p;
+            pt::compile_loglik(t, p);
+            tll[b].op_first = (int32_t)ops.size();
+            tll[b].n_first = (int32_t)p.size();
+            ops.insert(ops.end(), p.begin(), p.end());
+        }
+        if (kinds & PT_PLAN_GRAD) {
+            std::vector<Op> p;
+            pt::compile_grad(t, p);
+            tgr[b].op_first = (int32_t)ops.size();
+            tgr[b].n_first = (int32_t)p.size();
+            ops.insert(ops.end(), p.begin(), p.end());
+        }
+        if (kinds & PT_PLAN_OPTIMIZE) {
+            const uint8_t *m = mask ? mask + base.edge_off : nullptr;
+            bool any = !m;
+            for (int e = 0; m && e < E; ++e) any |= m[e] != 0;
+            std::vector<Op> p1, p2;
+            if (any) pt::compile_optimize(t, m, p1, p2);
+            else pt::compile_loglik(t, p1);
+            top[b].op_first = (int32_t)ops.size();
+            top[b].n_first = (int32_t)p1.size();
+            ops.insert(ops.end(), p1.begin(), p1.end());
+            top[b].op_steady = (int32_t)ops.size();
+            top[b].n_steady = (int32_t)p2.size();
+            ops.insert(ops.end(), p2.begin(), p2.end());
+            cost[b] = (double)items * (double)(p2.size() + 1);
+        }
+    }
+    pl->n_tiles = tiles;
+
+    // arena cap
+    int64_t need = clv_off * (int64_t)store_bytes(precision) + cnt_off * 2 + pm_off * 8 +
+                   (int64_t)ops.size() * sizeof(Op) + (int64_t)tiles * std::max(1, pl->max_E) * 24 +
+                   (int64_t)NE * 16 + (int64_t)B * 3 * sizeof(TreeDev);
+    int64_t cap = arena_cap();
+    if (cap > 0 && need > cap)
+        return fail(PT_ENOMEM, "batch needs " + std::to_string(need) + " device bytes, over PT_ARENA_CAP_BYTES");
+
+    int dev_prev = 0;
+    PT_HIP(hipGetDevice(&dev_prev));
+    PT_HIP(hipSetDevice(ctx->device));
+    // descriptors
+    std::vector<AlnDev> ad(n_alns);
+    for (int i = 0; i < n_alns; ++i) ad[i] = alns[i]->desc;
+    if ((st = dev_alloc(pl.get(), &pl->d_alns, sizeof(AlnDev) * n_alns))) return st;
+    PT_HIP(hipMemcpy(pl->d_alns, ad.data(), sizeof(AlnDev) * n_alns, hipMemcpyHostToDevice));
+    if ((st = dev_alloc(pl.get(), &pl->d_ops, sizeof(Op) * ops.size()))) return st;
+    if (!ops.empty()) PT_HIP(hipMemcpy(pl->d_ops, ops.data(), sizeof(Op) * ops.size(), hipMemcpyHostToDevice));
+    auto up_trees = [&](std::vector<TreeDev> &v, TreeDev **d) -> pt_status {
+        pt_status s2 = dev_alloc(pl.get(), d, sizeof(TreeDev) * std::max(1, B));
+        if (s2) return s2;
+        if (B) PT_HIP(hipMemcpy(*d, v.data(), sizeof(TreeDev) * B, hipMemcpyHostToDevice));
+        return PT_OK;
+    };
+    if (kinds & PT_PLAN_LOGLIK) if ((st = up_trees(tll, &pl->d_trees_ll))) return st;
+    if (kinds & PT_PLAN_GRAD) if ((st = up_trees(tgr, &pl->d_trees_gr))) return st;
+    if (kinds & PT_PLAN_OPTIMIZE) if ((st = up_trees(top, &pl->d_trees_opt))) return st;
+    if ((st = dev_alloc(pl.get(), &pl->d_edge_tree, sizeof(int32_t) * std::max<int64_t>(1, NE)))) return st;
+    if (NE) PT_HIP(hipMemcpy(pl->d_edge_tree, edge_tree.data(), sizeof(int32_t) * NE, hipMemcpyHostToDevice));
+    if (tiles) {
+        if ((st = dev_alloc(pl.get(), &pl->d_tile_tree, sizeof(int32_t) * tiles))) return st;
+        PT_HIP(hipMemcpy(pl->d_tile_tree, tile_tree.data(), sizeof(int32_t) * tiles, hipMemcpyHostToDevice));
+        if ((st = dev_alloc(pl.get(), &pl->d_part, sizeof(double) * 3 * (size_t)tiles * std::max(1, pl->max_E)))) return st;
+    }
+    if (kinds & PT_PLAN_OPTIMIZE) {
+        std::vector<int32_t> order(B);
+        std::iota(order.begin(), order.end(), 0);
+        std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+        if ((st = dev_alloc(pl.get(), &pl->d_order, sizeof(int32_t) * std::max(1, B)))) return st;
+        if (B) PT_HIP(hipMemcpy(pl->d_order, order.data(), sizeof(int32_t) * B, hipMemcpyHostToDevice));
+        if ((st = dev_alloc(pl.get(), &pl->d_queue, sizeof(int32_t) * 4))) return st;
+        if ((st = dev_alloc(pl.get(), &pl->d_scratch, sizeof(double) * std::max<int64_t>(1, NE)))) return st;
+    }
+    if ((st = dev_alloc(pl.get(), &pl->d_clv, (size_t)clv_off * store_bytes(precision)))) return st;
+    if ((st = dev_alloc(pl.get(), &pl->d_cnt, (size_t)cnt_off * 2))) return st;
+    if ((st = dev_alloc(pl.get(), &pl->d_pmat, (size_t)pm_off * 8))) return st;
+    PT_HIP(hipSetDevice(dev_prev));
+
+    pl->kp = kp_of_plan(alns, n_alns);
+    pl->lds_tiles = 0;
+    for (int b = 0; b < B; ++b) {
+        const AlnDev &a2 = alns[trees->aln_index[b]]->desc;
+        pl->lds_tiles = std::max(pl->lds_tiles, (size_t)pl->tree_E[b] * a2.Kp * 16 * 8);
+        pl->lds_opt = std::max(pl->lds_opt, (size_t)pl->tree_E[b] * (a2.Kp * 16 + 1) * 8);
+    }
+    if (kinds & PT_PLAN_OPTIMIZE) {
+        auto it = ctx->tuned.find(std::make_tuple(precision, pl->kp, pl->max_items));
+        if (it != ctx->tuned.end()) {
+            pl->opt_block = it->second.first;
+            pl->opt_items = it->second.second;
+        } else {
+            pick_shape(pl.get());
+        }
+        if (!pl->opt_block) return fail(PT_EUNSUPPORTED, "no launch shape covers the pattern count");
+    }
+    *out = pl.release();
+    return PT_OK;
+}
+
+pt::BatchArgs batch_args(const pt_plan *pl, const TreeDev *trees, int part_cols) {
+    pt::BatchArgs a{};
+    a.trees = trees;
+    a.alns = pl->d_alns;
+    a.ops = pl->d_ops;
+    a.tile_tree = pl->d_tile_tree;
+    a.edge_tree = pl->d_edge_tree;
+    a.order = pl->d_order;
+    a.clv = pl->d_clv;
+    a.cnt = pl->d_cnt;
+    a.pmat = pl->d_pmat;
+    a.part = pl->d_part;
+    a.queue = pl->d_queue;
+    a.n_trees = pl->n_trees;
+    a.n_tiles = pl->n_tiles;
+    a.n_edges = pl->n_edges;
+    a.part_cols = part_cols;
+    return a;
+}
+
+int opt_grid(pt_plan *pl) {
+    int per_cu = pt::optimize_blocks_per_cu(pl->precision, pl->opt_block, pl->opt_items, pl->lds_opt);
+    if (per_cu < 1) per_cu = 1;
+    long cap = (long)per_cu * std::max(1, pl->ctx->n_cu);
+    return (int)std::max(1L, std::min<long>(pl->n_trees, cap));
+}
+
+// Enqueue the kernels of one plan call.
+pt_status enqueue(pt_plan *pl, int kind, const double *brlen_c, double *brlen, const pt::OptParams *op,
+                  double *lnl, int32_t *passes, int32_t *status, double *grad, double *hess, hipStream_t s) {
+    if (pl->n_trees == 0) return PT_OK;
+    hipError_t e = hipSuccess;
+    if (kind == PT_PLAN_LOGLIK || kind == PT_PLAN_GRAD) {
+        const bool g = kind == PT_PLAN_GRAD;
+        pt::BatchArgs a = batch_args(pl, g ? pl->d_trees_gr : pl->d_trees_ll, g ? std::max(1, pl->max_E) : 1);
+        if ((e = pt::launch_pmat(a, brlen_c, s)) != hipSuccess) goto bad;
+        if ((e = pt::launch_tiles(pl->precision, g, a, brlen_c, pl->lds_tiles, s)) != hipSuccess) goto bad;
+        if ((e = pt::launch_reduce(g, a, lnl, grad, hess, s)) != hipSuccess) goto bad;
+        return PT_OK;
+    }
+    {
+        pt::BatchArgs a = batch_args(pl, pl->d_trees_opt, 1);
+        if ((e = pt::launch_fill_i32(pl->d_queue, 0, 1, s)) != hipSuccess) goto bad;
+        if (!pl->opt_grid) pl->opt_grid = opt_grid(pl);
+        if ((e = pt::launch_optimize(pl->precision, pl->opt_block, pl->opt_items, pl->opt_grid, a, brlen, *op, lnl,
+                                     passes, status, pl->lds_opt, s)) != hipSuccess)
+            goto bad;
+        return PT_OK;
+    }
+bad:
+    return fail(PT_EDEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
+}
+
+// Run directly, or through a graph captured once per argument set.
+pt_status run(pt_plan *pl, int kind, const double *brlen_c, double *brlen, const pt::OptParams *op, double *lnl,
+              int32_t *passes, int32_t *status, double *grad, double *hess, hipStream_t s) {
+    PT_HIP(hipSetDevice(pl->ctx->device));
+    if (!pl->graphs || s == nullptr) return enqueue(pl, kind, brlen_c, brlen, op, lnl, passes, status, grad, hess, s);
+    std::vector<uint64_t> key = {(uint64_t)kind, (uint64_t)(uintptr_t)brlen_c, (uint64_t)(uintptr_t)brlen,
+                                 (uint64_t)(uintptr_t)lnl, (uint64_t)(uintptr_t)passes, (uint64_t)(uintptr_t)status,
+                                 (uint64_t)(uintptr_t)grad, (uint64_t)(uintptr_t)hess, (uint64_t)(uintptr_t)s};
+    if (op) {
+        const uint64_t *w = reinterpret_cast<const uint64_t *>(op);
+        key.insert(key.end(), w, w + sizeof(pt::OptParams) / 8);
+    }
+    auto it = pl->execs.find(key);
+    if (it == pl->execs.end()) {
+        hipGraph_t g = nullptr;
+        PT_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        pt_status st = enqueue(pl, kind, brlen_c, brlen, op, lnl, passes, status, grad, hess, s);
+        hipError_t e2 = hipStreamEndCapture(s, &g);
+        if (st) { if (g) (void)hipGraphDestroy(g); return st; }
+        if (e2 != hipSuccess) return fail(PT_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e2));
+        hipGraphExec_t ex = nullptr;
+        hipError_t e3 = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e3 != hipSuccess) return fail(PT_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e3));
+        it = pl->execs.emplace(key, ex).first;
+    }
+    PT_HIP(hipGraphLaunch(it->second, s));
+    return PT_OK;
+}
+
+// Split trees [0, n) into consecutive chunks whose plans fit the arena cap.
+pt_status chunks_for(pt_aln *const *alns, const pt_trees *trees, const std::vector<int> &ntx, int precision,
+                     int kinds, std::vector<std::pair<int, int>> &out) {
+    const int64_t cap = arena_cap();
+    const int B = trees->n_trees;
+    if (cap <= 0) {
+        out.push_back({0, B});
+        return PT_OK;
+    }
+    int64_t used = 0;
+    int start = 0;
+    for (int b = 0; b < B; ++b) {
+        int64_t need = tree_bytes(ntx[b], alns[trees->aln_index[b]]->desc, precision, kinds) + 4096;
+        if (need > cap) return fail(PT_ENOMEM, "tree " + std::to_string(b) + " alone exceeds PT_ARENA_CAP_BYTES");
+        if (used + need > cap && b > start) {
+            out.push_back({start, b});
+            start = b;
+            used = 0;
+        }
+        used += need;
+    }
+    out.push_back({start, B});
+    return PT_OK;
+}
+
+// Host-pointer batch driver shared by the three batch calls.
+pt_status host_batch(pt_ctx *ctx, pt_aln *const *alns, int32_t n_alns, const pt_trees *trees, double *brlen_io,
+                     const double *brlen_in, const uint8_t *mask, const pt_opt *opt, int precision, int kind,
+                     double *lnl_out, int32_t *passes_out, int32_t *status_out, double *grad_out, double *hess_out) {
+    std::vector<int> ntx;
+    pt_status st = check_trees(ctx, alns, n_alns, trees, ntx);
+    if (st) return st;
+    if (precision != PT_FP32 && precision != PT_FP64) return fail(PT_EINVAL, "precision must be PT_FP64 or PT_FP32");
+    const int B = trees->n_trees;
+    const int64_t NE = B ? trees->edge_offset[B] : 0;
+    const double *lens = brlen_io ? brlen_io : brlen_in;
+    if ((st = check_lengths(lens, NE))) return st;
+    if (B > 0 && !lnl_out) return fail(PT_EINVAL, "lnl_out is NULL");
+    if (kind == PT_PLAN_GRAD && NE > 0 && !grad_out) return fail(PT_EINVAL, "grad_out is NULL");
+    pt_opt o;
+    if (kind == PT_PLAN_OPTIMIZE) {
+        if (opt) o = *opt; else pt_opt_default(precision, &o);
+        if ((st = check_opt(o))) return st;
+    }
+    std::vector<std::pair<int, int>> parts;
+    if ((st = chunks_for(alns, trees, ntx, precision, kind, parts))) return st;
+    // validate every chunk before any device work
+    std::vector<std::unique_ptr<pt_plan, void (*)(pt_plan *)>> plans;
+    std::vector<pt_trees> subs;
+    for (auto &pr : parts) {
+        pt_trees sub;
+        sub.n_trees = pr.second - pr.first;
+        sub.aln_index = trees->aln_index + pr.first;
+        sub.edges = trees->edges + 2 * trees->edge_offset[pr.first];
+        subs.push_back(sub);
+    }
+    std::vector<std::vector<int64_t>> offs(parts.size());
+    for (size_t c = 0; c < parts.size(); ++c) {
+        const auto &pr = parts[c];
+        offs[c].resize(pr.second - pr.first + 1);
+        for (int b = pr.first; b <= pr.second; ++b) offs[c][b - pr.first] = trees->edge_offset[b] - trees->edge_offset[pr.first];
+        subs[c].edge_offset = offs[c].data();
+    }
+    // outputs are written only after every chunk has succeeded
+    std::vector<double> lnl(B), lens_out(lens, lens + NE), grad(kind == PT_PLAN_GRAD ? NE : 0),
+        hess(kind == PT_PLAN_GRAD && hess_out ? NE : 0);
+    std::vector<int32_t> passes(B), status(B);
+    for (size_t c = 0; c < parts.size(); ++c) {
+        const int b0 = parts[c].first, nb = parts[c].second - parts[c].first;
+        const int64_t e0 = trees->edge_offset[b0], ne = trees->edge_offset[parts[c].second] - e0;
+        pt_plan *raw = nullptr;
+        st = plan_build(ctx, alns, n_alns, &subs[c], mask ? mask + e0 : nullptr, precision, kind, &raw);
+        if (st) return st;
+        std::unique_ptr<pt_plan, void (*)(pt_plan *)> pl(raw, free_plan);
+        PT_HIP(hipSetDevice(ctx->device));
+        double *d_len = nullptr, *d_lnl = nullptr, *d_g = nullptr, *d_h = nullptr;
+        int32_t *d_ps = nullptr, *d_st = nullptr;
+        if ((st = dev_alloc(pl.get(), &d_len, sizeof(double) * std::max<int64_t>(1, ne)))) return st;
+        if ((st = dev_alloc(pl.get(), &d_lnl, sizeof(double) * std::max(1, nb)))) return st;
+        if (ne) PT_HIP(hipMemcpyAsync(d_len, lens + e0, sizeof(double) * ne, hipMemcpyHostToDevice, ctx->stream));
+        pt::OptParams op{};
+        if (kind == PT_PLAN_OPTIMIZE) {
+            op = to_params(o);
+            if ((st = dev_alloc(pl.get(), &d_ps, sizeof(int32_t) * std::max(1, nb)))) return st;
+            if ((st = dev_alloc(pl.get(), &d_st, sizeof(int32_t) * std::max(1, nb)))) return st;
+            st = enqueue(pl.get(), kind, nullptr, d_len, &op, d_lnl, d_ps, d_st, nullptr, nullptr, ctx->stream);
+        } else if (kind == PT_PLAN_GRAD) {
+            if ((st = dev_alloc(pl.get(), &d_g, sizeof(double) * std::max<int64_t>(1, ne)))) return st;
+            if (hess_out && (st = dev_alloc(pl.get(), &d_h, sizeof(double) * std::max<int64_t>(1, ne)))) return st;
+            st = enqueue(pl.get(), kind, d_len, nullptr, nullptr, d_lnl, nullptr, nullptr, d_g, d_h, ctx->stream);
+        } else {
+            st = enqueue(pl.get(), kind, d_len, nullptr, nullptr, d_lnl, nullptr, nullptr, nullptr, nullptr, ctx->stream);
+        }
+        if (st) return st;
+        if (nb) PT_HIP(hipMemcpyAsync(lnl.data() + b0, d_lnl, sizeof(double) * nb, hipMemcpyDeviceToHost, ctx->stream));
+        if (kind == PT_PLAN_OPTIMIZE && nb) {
+            PT_HIP(hipMemcpyAsync(lens_out.data() + e0, d_len, sizeof(double) * ne, hipMemcpyDeviceToHost, ctx->stream));
+            PT_HIP(hipMemcpyAsync(passes.data() + b0, d_ps, sizeof(int32_t) * nb, hipMemcpyDeviceToHost, ctx->stream));
+            PT_HIP(hipMemcpyAsync(status.data() + b0, d_st, sizeof(int32_t) * nb, hipMemcpyDeviceToHost, ctx->stream));
+        }
+        if (kind == PT_PLAN_GRAD && ne) {
+            PT_HIP(hipMemcpyAsync(grad.data() + e0, d_g, sizeof(double) * ne, hipMemcpyDeviceToHost, ctx->stream));
+            if (d_h) PT_HIP(hipMemcpyAsync(hess.data() + e0, d_h, sizeof(double) * ne, hipMemcpyDeviceToHost, ctx->stream));
+        }
+        PT_HIP(hipStreamSynchronize(ctx->stream));
+    }
+    std::copy(lnl.begin(), lnl.end(), lnl_out);
+    if (kind == PT_PLAN_OPTIMIZE) {
+        std::copy(lens_out.begin(), lens_out.end(), brlen_io);
+        if (passes_out) std::copy(passes.begin(), passes.end(), passes_out);
+        if (status_out) std::copy(status.begin(), status.end(), status_out);
+    }
+    if (kind == PT_PLAN_GRAD) {
+        std::copy(grad.begin(), grad.end(), grad_out);
+        if (hess_out) std::copy(hess.begin(), hess.end(), hess_out);
+    }
+    return PT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *pt_last_error(void) { return g_err.c_str(); }
+
+pt_status pt_ctx_create(int32_t device, pt_ctx **out) {
+    if (!out) return fail(PT_EINVAL, "out is NULL");
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess || n == 0) return fail(PT_EDEVICE, "no HIP device available");
+    if (device < 0 || device >= n) return fail(PT_EINVAL, "device index out of range");
+    auto *c = new pt_ctx;
+    c->device = device;
+    hipDeviceProp_t prop;
+    if ((e = hipSetDevice(device)) != hipSuccess || (e = hipGetDeviceProperties(&prop, device)) != hipSuccess ||
+        (e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking)) != hipSuccess) {
+        delete c;
+        return fail(PT_EDEVICE, std::string("device set-up: ") + hipGetErrorString(e));
+    }
+    c->n_cu = prop.multiProcessorCount;
+    *out = c;
+    return PT_OK;
+}
+
+void pt_ctx_destroy(pt_ctx *ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+}
+
+pt_status pt_aln_create(pt_ctx *ctx, int32_t n_taxa, int32_t n_patterns, const uint8_t *tips, const double *weights,
+                        const pt_model *model, pt_aln **out) {
+    if (!ctx || !tips || !weights || !model || !out) return fail(PT_EINVAL, "NULL argument");
+    if (n_taxa < 2) return fail(PT_EINVAL, "n_taxa must be >= 2");
+    if (n_patterns < 1) return fail(PT_EINVAL, "n_patterns must be >= 1");
+    for (int64_t i = 0; i < (int64_t)n_taxa * n_patterns; ++i)
+        if (tips[i] == 0 || tips[i] > 15) return fail(PT_EINVAL, "tip codes must be in 1..15");
+    for (int p = 0; p < n_patterns; ++p)
+        if (!(weights[p] > 0.0) || !std::isfinite(weights[p])) return fail(PT_EINVAL, "weights must be finite and > 0");
+    AlnDev d{};
+    std::string err;
+    pt_status st = pt::build_model(*model, d, err);
+    if (st) return fail(st, err);
+    d.n_taxa = n_taxa;
+    d.P = n_patterns;
+    auto *a = new pt_aln;
+    a->ctx = ctx;
+    a->n_taxa = n_taxa;
+    a->P = n_patterns;
+    hipError_t e;
+    size_t tb = (size_t)n_taxa * n_patterns;
+    if ((e = hipSetDevice(ctx->device)) != hipSuccess || (e = hipMalloc(&a->d_tips, tb)) != hipSuccess ||
+        (e = hipMalloc(&a->d_w, sizeof(double) * n_patterns)) != hipSuccess ||
+        (e = hipMemcpy(a->d_tips, tips, tb, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(a->d_w, weights, sizeof(double) * n_patterns, hipMemcpyHostToDevice)) != hipSuccess) {
+        pt_aln_destroy(a);
+        return fail(e == hipErrorOutOfMemory ? PT_ENOMEM : PT_EDEVICE, std::string("alignment upload: ") + hipGetErrorString(e));
+    }
+    d.tips = a->d_tips;
+    d.w = a->d_w;
+    a->desc = d;
+    *out = a;
+    return PT_OK;
+}
+
+void pt_aln_destroy(pt_aln *aln) {
+    if (!aln) return;
+    if (aln->d_tips) (void)hipFree(aln->d_tips);
+    if (aln->d_w) (void)hipFree(aln->d_w);
+    delete aln;
+}
+
+void pt_opt_default(int32_t precision, pt_opt *out) {
+    if (!out) return;
+    out->t_min = 1e-8;
+    out->t_max = 100.0;
+    out->max_passes = 200;
+    out->max_newton = 32;
+    if (precision == PT_FP32) {
+        out->tol_lnl = 1e-5;
+        out->tol_t = 1e-3;
+        out->tol_newton = 1e-6;
+    } else {
+        out->tol_lnl = 1e-8;
+        out->tol_t = 1e-5;
+        out->tol_newton = 1e-9;
+    }
+}
+
+pt_status pt_batch_loglik(pt_ctx *ctx, pt_aln *const *alns, int32_t n_alns, const pt_trees *trees, const double *brlen,
+                          int32_t precision, double *lnl_out) {
+    return host_batch(ctx, alns, n_alns, trees, nullptr, brlen, nullptr, nullptr, precision, PT_PLAN_LOGLIK, lnl_out,
+                      nullptr, nullptr, nullptr, nullptr);
+}
+
+pt_status pt_batch_optimize_branches(pt_ctx *ctx, pt_aln *const *alns, int32_t n_alns, const pt_trees *trees,
+                                     double *brlen_inout, const uint8_t *opt_mask, const pt_opt *opt,
+                                     int32_t precision, double *lnl_out, int32_t *passes_out, int32_t *status_out) {
+    if (!brlen_inout && trees && trees->n_trees > 0) return fail(PT_EINVAL, "brlen_inout is NULL");
+    return host_batch(ctx, alns, n_alns, trees, brlen_inout, nullptr, opt_mask, opt, precision, PT_PLAN_OPTIMIZE,
+                      lnl_out, passes_out, status_out, nullptr, nullptr);
+}
+
+pt_status pt_batch_branch_grad(pt_ctx *ctx, pt_aln *const *alns, int32_t n_alns, const pt_trees *trees,
+                               const double *brlen, int32_t precision, double *lnl_out, double *grad_out,
+                               double *hess_diag_out) {
+    return host_batch(ctx, alns, n_alns, trees, nullptr, brlen, nullptr, nullptr, precision, PT_PLAN_GRAD, lnl_out,
+                      nullptr, nullptr, grad_out, hess_diag_out);
+}
+
+pt_status pt_plan_create(pt_ctx *ctx, pt_aln *const *alns, int32_t n_alns, const pt_trees *trees,
+                         const uint8_t *opt_mask, int32_t precision, int32_t kinds, pt_plan **out) {
+    if (!out) return fail(PT_EINVAL, "out is NULL");
+    return plan_build(ctx, alns, n_alns, trees, opt_mask, precision, kinds, out);
+}
+
+void pt_plan_destroy(pt_plan *plan) { free_plan(plan); }
+
+pt_status pt_plan_set_graphs(pt_plan *plan, int32_t enable) {
+    if (!plan) return fail(PT_EINVAL, "plan is NULL");
+    plan->graphs = enable != 0;
+    return PT_OK;
+}
+
+pt_status pt_plan_loglik(pt_plan *plan, const double *d_brlen, double *d_lnl, void *stream) {
+    if (!plan || !(plan->kinds & PT_PLAN_LOGLIK)) return fail(PT_EINVAL, "plan was not created with PT_PLAN_LOGLIK");
+    if (plan->n_trees && (!d_brlen || !d_lnl)) return fail(PT_EINVAL, "NULL device pointer");
+    return run(plan, PT_PLAN_LOGLIK, d_brlen, nullptr, nullptr, d_lnl, nullptr, nullptr, nullptr, nullptr,
+               (hipStream_t)stream);
+}
+
+pt_status pt_plan_optimize(pt_plan *plan, double *d_brlen_inout, const pt_opt *opt, double *d_lnl, int32_t *d_passes,
+                           int32_t *d_status, void *stream) {
+    if (!plan || !(plan->kinds & PT_PLAN_OPTIMIZE)) return fail(PT_EINVAL, "plan was not created with PT_PLAN_OPTIMIZE");
+    if (plan->n_trees && (!d_brlen_inout || !d_lnl)) return fail(PT_EINVAL, "NULL device pointer");
+    pt_opt o;
+    if (opt) o = *opt; else pt_opt_default(plan->precision, &o);
+    pt_status st = check_opt(o);
+    if (st) return st;
+    pt::OptParams p = to_params(o);
+    return run(plan, PT_PLAN_OPTIMIZE, nullptr, d_brlen_inout, &p, d_lnl, d_passes, d_status, nullptr, nullptr,
+               (hipStream_t)stream);
+}
+
+pt_status pt_plan_grad(pt_plan *plan, const double *d_brlen, double *d_lnl, double *d_grad, double *d_hess,
+                       void *stream) {
+    if (!plan || !(plan->kinds & PT_PLAN_GRAD)) return fail(PT_EINVAL, "plan was not created with PT_PLAN_GRAD");
+    if (plan->n_trees && (!d_brlen || !d_lnl || !d_grad)) return fail(PT_EINVAL, "NULL device pointer");
+    return run(plan, PT_PLAN_GRAD, d_brlen, nullptr, nullptr, d_lnl, nullptr, nullptr, d_grad, d_hess,
+               (hipStream_t)stream);
+}
+
+pt_status pt_plan_autotune(pt_plan *plan, const double *d_brlen, const pt_opt *opt, int32_t *block, int32_t *items) {
+    if (!plan || !(plan->kinds & PT_PLAN_OPTIMIZE)) return fail(PT_EINVAL, "plan was not created with PT_PLAN_OPTIMIZE");
+    if (plan->n_trees == 0) return PT_OK;
+    if (!d_brlen) return fail(PT_EINVAL, "d_brlen is NULL");
+    pt_opt o;
+    if (opt) o = *opt; else pt_opt_default(plan->precision, &o);
+    pt_status st = check_opt(o);
+    if (st) return st;
+    pt::OptParams p = to_params(o);
+    PT_HIP(hipSetDevice(plan->ctx->device));
+    hipStream_t s = plan->ctx->stream;
+    double *d_lnl = nullptr;
+    if ((st = dev_alloc(plan, &d_lnl, sizeof(double) * plan->n_trees))) return st;
+    static const int blocks[3] = {256, 512, 1024};
+    static const int nis[6] = {1, 2, 4, 8, 12, 16};
+    int best_b = plan->opt_block, best_i = plan->opt_items;
+    float best_ms = 1e30f;
+    hipEvent_t e0, e1;
+    PT_HIP(hipEventCreate(&e0));
+    PT_HIP(hipEventCreate(&e1));
+    const size_t nb = sizeof(double) * plan->n_edges;
+    long min_cap = 0;
+    for (int ni : nis)
+        for (int bs : blocks)
+            if ((long)bs * ni >= plan->max_items && (!min_cap || (long)bs * ni < min_cap)) min_cap = (long)bs * ni;
+    for (int ni : nis)
+        for (int bs : blocks) {
+            long cap = (long)bs * ni;
+            if (!pt::optimize_shape_supported(bs, ni) || cap < plan->max_items || cap > 4 * min_cap) continue;
+            if (pt::optimize_blocks_per_cu(plan->precision, bs, ni, plan->lds_opt) < 1) continue;
+            plan->opt_block = bs;
+            plan->opt_items = ni;
+            plan->opt_grid = 0;
+            float ms_best_trial = 1e30f;
+            for (int rep = 0; rep < 2; ++rep) {
+                PT_HIP(hipMemcpyAsync(plan->d_scratch, d_brlen, nb, hipMemcpyDeviceToDevice, s));
+                PT_HIP(hipEventRecord(e0, s));
+                st = enqueue(plan, PT_PLAN_OPTIMIZE, nullptr, plan->d_scratch, &p, d_lnl, nullptr, nullptr, nullptr,
+                             nullptr, s);
+                if (st) return st;
+                PT_HIP(hipEventRecord(e1, s));
+                PT_HIP(hipEventSynchronize(e1));
+                float ms = 0;
+                PT_HIP(hipEventElapsedTime(&ms, e0, e1));
+                ms_best_trial = std::min(ms_best_trial, ms);
+            }
+            if (ms_best_trial < best_ms) {
+                best_ms = ms_best_trial;
+                best_b = bs;
+                best_i = ni;
+            }
+        }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    plan->opt_block = best_b;
+    plan->opt_items = best_i;
+    plan->opt_grid = 0;
+    for (auto &kv : plan->execs) (void)hipGraphExecDestroy(kv.second);
+    plan->execs.clear();
+    plan->ctx->tuned[std::make_tuple(plan->precision, plan->kp, plan->max_items)] = {best_b, best_i};
+    if (block) *block = best_b;
+    if (items) *items = best_i;
+    return PT_OK;
+}
+
+pt_status pt_plan_info(const pt_plan *plan, int32_t *n_trees, int64_t *n_edges, int64_t *device_bytes) {
+    if (!plan) return fail(PT_EINVAL, "plan is NULL");
+    if (n_trees) *n_trees = plan->n_trees;
+    if (n_edges) *n_edges = plan->n_edges;
+    if (device_bytes) *device_bytes = plan->device_bytes;
+    return PT_OK;
+}
+
+pt_status pt_model_info(const pt_model *model, double *cat_rates, double *U, double *Uinv, double *lam) {
+    if (!model) return fail(PT_EINVAL, "model is NULL");
+    AlnDev d{};
+    std::string err;
+    pt_status st = pt::build_model(*model, d, err);
+    if (st) return fail(st, err);
+    if (cat_rates) std::copy(d.rate, d.rate + d.K, cat_rates);
+    if (U) std::copy(d.U, d.U + 16, U);
+    if (Uinv) std::copy(d.Uinv, d.Uinv + 16, Uinv);
+    if (lam) std::copy(d.lam, d.lam + 4, lam);
+    return PT_OK;
+}
+
+pt_status pt_tree_check(int32_t n_taxa, const int32_t *edges) {
+    if (!edges) return fail(PT_EINVAL, "edges is NULL");
+    pt::Tree t;
+    std::string err;
+    pt_status st = pt::build_tree(n_taxa, edges, t, err);
+    return st ? fail(st, err) : PT_OK;
+}
+
+pt_status pt_nni_neighbors(int32_t n, const int32_t *edges, const double *brlen, int32_t *out_edges, double *out_brlen,
+                           int32_t *out_touched) {
+    if (!edges || !out_edges) return fail(PT_EINVAL, "NULL argument");
+    std::string err;
+    pt_status st = pt::nni_neighbors(n, edges, brlen, out_edges, out_brlen, out_touched, err);
+    return st ? fail(st, err) : PT_OK;
+}
+
+pt_status pt_topology_key(int32_t n, const int32_t *edges, uint64_t *out) {
+    if (!edges || !out) return fail(PT_EINVAL, "NULL argument");
+    std::string err;
+    pt_status st = pt::topology_key(n, edges, out, err);
+    return st ? fail(st, err) : PT_OK;
+}
+
+}  // extern "C"

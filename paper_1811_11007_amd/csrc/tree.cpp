@@ -1,0 +1,287 @@
+// tree.cpp -- tree validation, per-tree kernel programs and host topology ops.
+//
+// Directional partials.  For internal node v and its neighbour u, slot
+// (v, u) holds the partial likelihood of v's side of edge (v, u), at v:
+// the product over v's two other neighbours c of P(t_vc) times the partial of
+// c's side.  With every slot valid, lnL and the derivatives across any edge
+// (u, v) follow from slots (u, v) and (v, u) alone (re-rooting on an edge,
+// the pulley principle), which is what the edge steps of coordinate-wise
+// branch optimisation need.  The compiler simulates which slots a length
+// change invalidates and emits exactly the updates each step needs.
+#include <algorithm>
+#include <cstring>
+#include <functional>
+
+#include "pt_internal.hpp"
+
+namespace pt {
+
+pt_status build_tree(int n, const int32_t *edges, Tree &t, std::string &err) {
+    if (n < 2) { err = "a tree needs at least 2 taxa"; return PT_EINVAL; }
+    t.n = n;
+    t.n_nodes = n == 2 ? 2 : 2 * n - 2;
+    t.n_edges = n == 2 ? 1 : 2 * n - 3;
+    t.ends.assign(edges, edges + 2 * t.n_edges);
+    t.nbr.assign(3 * t.n_nodes, -1);
+    t.nedge.assign(3 * t.n_nodes, -1);
+    t.deg.assign(t.n_nodes, 0);
+    for (int e = 0; e < t.n_edges; ++e) {
+        int a = edges[2 * e], b = edges[2 * e + 1];
+        if (a < 0 || b < 0 || a >= t.n_nodes || b >= t.n_nodes) {
+            err = "edge " + std::to_string(e) + ": node id out of range";
+            return PT_EINVAL;
+        }
+        if (a == b) { err = "edge " + std::to_string(e) + " is a self-loop"; return PT_EINVAL; }
+        if (t.deg[a] >= 3 || t.deg[b] >= 3) {
+            err = "node of degree > 3 at edge " + std::to_string(e);
+            return PT_EINVAL;
+        }
+        t.nbr[3 * a + t.deg[a]] = b; t.nedge[3 * a + t.deg[a]++] = e;
+        t.nbr[3 * b + t.deg[b]] = a; t.nedge[3 * b + t.deg[b]++] = e;
+    }
+    for (int v = 0; v < t.n_nodes; ++v) {
+        int want = v < n ? 1 : 3;
+        if (t.deg[v] != want) {
+            err = "node " + std::to_string(v) + " has degree " + std::to_string(t.deg[v]) +
+                  ", expected " + std::to_string(want);
+            return PT_EINVAL;
+        }
+    }
+    std::vector<char> seen(t.n_nodes, 0);
+    std::vector<int> stack{0};
+    seen[0] = 1;
+    int count = 0;
+    while (!stack.empty()) {
+        int v = stack.back();
+        stack.pop_back();
+        ++count;
+        for (int j = 0; j < t.deg[v]; ++j)
+            if (!seen[t.nbr[3 * v + j]]) { seen[t.nbr[3 * v + j]] = 1; stack.push_back(t.nbr[3 * v + j]); }
+    }
+    if (count != t.n_nodes) { err = "edge list is not connected (contains a cycle)"; return PT_EINVAL; }
+    return PT_OK;
+}
+
+namespace {
+
+// Slot bookkeeping shared by the three compilers.
+struct Slots {
+    const Tree &t;
+    std::vector<uint8_t> valid;
+    std::vector<std::vector<uint64_t>> deps;  // per slot: bitset of edges inside
+    int words;
+    std::vector<Op> *out = nullptr;
+    int updates = 0;
+
+    explicit Slots(const Tree &tree) : t(tree), valid(tree.n_slots(), 0) {
+        words = (t.n_edges + 63) / 64;
+        deps.assign(t.n_slots(), std::vector<uint64_t>(words, 0));
+        std::vector<uint8_t> done(t.n_slots(), 0);
+        std::function<void(int)> fill = [&](int s) {
+            if (done[s]) return;
+            int v = s / 3 + t.n, j = s % 3;
+            for (int q = 0; q < 3; ++q) {
+                if (q == j) continue;
+                int c = t.nbr[3 * v + q], e = t.nedge[3 * v + q];
+                deps[s][e / 64] |= 1ull << (e % 64);
+                int r = ref(c, v);
+                if (r >= 0) {
+                    fill(r);
+                    for (int w = 0; w < words; ++w) deps[s][w] |= deps[r][w];
+                }
+            }
+            done[s] = 1;
+        };
+        for (int s = 0; s < t.n_slots(); ++s) fill(s);
+    }
+    // side of node v facing neighbour u: tip -(v+1) or slot index
+    int ref(int v, int u) const {
+        if (v < t.n) return -(v + 1);
+        for (int j = 0; j < 3; ++j)
+            if (t.nbr[3 * v + j] == u) return (v - t.n) * 3 + j;
+        return INT32_MIN;
+    }
+    void ensure(int r) {
+        if (r < 0 || valid[r]) return;
+        int v = r / 3 + t.n, j = r % 3;
+        int q0 = -1, q1 = -1;
+        for (int q = 0; q < 3; ++q) {
+            if (q == j) continue;
+            (q0 < 0 ? q0 : q1) = q;
+        }
+        int c0 = t.nbr[3 * v + q0], c1 = t.nbr[3 * v + q1];
+        int ra = ref(c0, v), rb = ref(c1, v);
+        ensure(ra);
+        ensure(rb);
+        Op op{};
+        op.code = OP_UPDATE;
+        op.dst = r;
+        op.a = ra; op.ea = t.nedge[3 * v + q0];
+        op.b = rb; op.eb = t.nedge[3 * v + q1];
+        out->push_back(op);
+        ++updates;
+        valid[r] = 1;
+    }
+    void touch(int e) {
+        for (int s = 0; s < t.n_slots(); ++s)
+            if (deps[s][e / 64] >> (e % 64) & 1) valid[s] = 0;
+    }
+};
+
+Op edge_op(int code, int e, int a, int b, int col) {
+    Op op{};
+    op.code = code;
+    op.dst = e;
+    op.a = a;
+    op.b = b;
+    op.ea = col;
+    return op;
+}
+
+}  // namespace
+
+void compile_loglik(const Tree &t, std::vector<Op> &ops) {
+    Slots s(t);
+    s.out = &ops;
+    int u = t.ends[0], v = t.ends[1];
+    int ra = s.ref(u, v), rb = s.ref(v, u);
+    s.ensure(ra);
+    s.ensure(rb);
+    ops.push_back(edge_op(OP_EVAL, 0, ra, rb, 0));
+}
+
+void compile_grad(const Tree &t, std::vector<Op> &ops) {
+    Slots s(t);
+    s.out = &ops;
+    for (int e = 0; e < t.n_edges; ++e) {
+        int u = t.ends[2 * e], v = t.ends[2 * e + 1];
+        int ra = s.ref(u, v), rb = s.ref(v, u);
+        s.ensure(ra);
+        s.ensure(rb);
+        ops.push_back(edge_op(OP_EVAL, e, ra, rb, e));
+    }
+}
+
+void compile_optimize(const Tree &t, const uint8_t *mask, std::vector<Op> &first,
+                      std::vector<Op> &steady) {
+    // depth-first edge order from the edge of leaf 0
+    std::vector<int> order;
+    std::function<void(int, int)> visit = [&](int x, int y) {
+        for (int j = 0; j < t.deg[y]; ++j) {
+            int z = t.nbr[3 * y + j];
+            if (z == x) continue;
+            order.push_back(t.nedge[3 * y + j]);
+            visit(y, z);
+        }
+    };
+    order.push_back(t.nedge[0]);
+    visit(0, t.nbr[0]);
+    if (t.n == 2) order.assign(1, 0);
+
+    Slots s(t);
+    auto pass = [&](std::vector<Op> &ops) {
+        s.out = &ops;
+        for (int e : order) {
+            if (mask && !mask[e]) continue;
+            int u = t.ends[2 * e], v = t.ends[2 * e + 1];
+            int ra = s.ref(u, v), rb = s.ref(v, u);
+            s.ensure(ra);
+            s.ensure(rb);
+            ops.push_back(edge_op(OP_NEWTON, e, ra, rb, 0));
+            s.touch(e);
+        }
+    };
+    pass(first);
+    // The validity pattern after a pass is the same for every pass that
+    // starts from it; iterate until the emitted program repeats.
+    std::vector<Op> prev;
+    pass(steady);
+    for (int guard = 0; guard < 8; ++guard) {
+        std::vector<Op> again;
+        pass(again);
+        if (again.size() == steady.size() &&
+            std::memcmp(again.data(), steady.data(), again.size() * sizeof(Op)) == 0)
+            break;
+        steady.swap(again);
+    }
+}
+
+// ------------------------------------------------------------- topology
+
+pt_status nni_neighbors(int n, const int32_t *edges, const double *brlen, int32_t *out_edges,
+                        double *out_brlen, int32_t *out_touched, std::string &err) {
+    if (n < 4) { err = "NNI needs n >= 4"; return PT_EINVAL; }
+    Tree t;
+    pt_status st = build_tree(n, edges, t, err);
+    if (st) return st;
+    const int E = t.n_edges;
+    int k = 0;
+    for (int e = 0; e < E; ++e) {
+        int u = edges[2 * e], v = edges[2 * e + 1];
+        if (u < n || v < n) continue;
+        int eu[2], ev[2], iu = 0, iv = 0;
+        for (int j = 0; j < 3; ++j) {
+            if (t.nedge[3 * u + j] != e) eu[iu++] = t.nedge[3 * u + j];
+            if (t.nedge[3 * v + j] != e) ev[iv++] = t.nedge[3 * v + j];
+        }
+        std::sort(eu, eu + 2);
+        std::sort(ev, ev + 2);
+        for (int w = 0; w < 2; ++w, ++k) {
+            int32_t *o = out_edges + (size_t)k * 2 * E;
+            std::memcpy(o, edges, sizeof(int32_t) * 2 * E);
+            int eb = eu[1], ec = ev[w];
+            for (int x = 0; x < 2; ++x) {
+                if (o[2 * eb + x] == u) o[2 * eb + x] = v;
+                if (o[2 * ec + x] == v) o[2 * ec + x] = u;
+            }
+            if (out_brlen && brlen) std::memcpy(out_brlen + (size_t)k * E, brlen, sizeof(double) * E);
+            if (out_touched) {
+                int32_t *tt = out_touched + (size_t)k * 5;
+                tt[0] = e; tt[1] = eb; tt[2] = ec; tt[3] = eu[0]; tt[4] = ev[1 - w];
+            }
+        }
+    }
+    return PT_OK;
+}
+
+pt_status topology_key(int n, const int32_t *edges, uint64_t *out, std::string &err) {
+    if (n < 4) { err = "topology keys need n >= 4"; return PT_EINVAL; }
+    Tree t;
+    pt_status st = build_tree(n, edges, t, err);
+    if (st) return st;
+    const int W = (n + 63) / 64;
+    // iterative post-order from leaf 0: leaf set below every node
+    std::vector<std::vector<uint64_t>> below(t.n_nodes, std::vector<uint64_t>(W, 0));
+    std::vector<int> parent(t.n_nodes, -1), order;
+    std::vector<int> stack{0};
+    parent[0] = 0;
+    while (!stack.empty()) {
+        int v = stack.back();
+        stack.pop_back();
+        order.push_back(v);
+        for (int j = 0; j < t.deg[v]; ++j) {
+            int c = t.nbr[3 * v + j];
+            if (parent[c] < 0 && c != 0) { parent[c] = v; stack.push_back(c); }
+        }
+    }
+    std::vector<std::vector<uint64_t>> splits;
+    for (int i = (int)order.size() - 1; i >= 1; --i) {
+        int v = order[i];
+        if (v < n) below[v][v / 64] |= 1ull << (v % 64);
+        int cnt = 0;
+        for (int w = 0; w < W; ++w) cnt += __builtin_popcountll(below[v][w]);
+        if (cnt >= 2 && cnt <= n - 2) splits.push_back(below[v]);
+        for (int w = 0; w < W; ++w) below[parent[v]][w] |= below[v][w];
+    }
+    if ((int)splits.size() != n - 3) { err = "internal error: split count"; return PT_EINTERNAL; }
+    std::sort(splits.begin(), splits.end(), [W](const std::vector<uint64_t> &a, const std::vector<uint64_t> &b) {
+        for (int w = W - 1; w >= 0; --w)
+            if (a[w] != b[w]) return a[w] < b[w];
+        return false;
+    });
+    for (int i = 0; i < n - 3; ++i)
+        for (int w = 0; w < W; ++w) out[(size_t)i * W + w] = splits[i][w];
+    return PT_OK;
+}
+
+}  // namespace pt
