@@ -1,0 +1,254 @@
+"""Benchmark: batched branch-length optimisation of NNI neighbour topologies.
+
+Workload (one step): full branch-length optimisation of all 48 NNI
+neighbours of a hill-climbed 27-taxon tree over 1949 sites (976 patterns)
+simulated under GTR+G4, lengths inherited from the parent, FP32 partials
+with per-pattern scaling and FP64 arithmetic and sums; one persistent
+kernel launch replayed from a HIP graph.  A step counts only if every
+topology's lnL is within 1e-4 of the FP64 CPU oracle's optimum (stored in
+tests/golden/c2_hillclimb.json by a script that calls only the oracle).
+
+Prints one JSON line.  Extra fields: the same batch in FP64, the plain
+per-topology GPU path (one tree per call, no graph), the pattern-tile
+pruning kernel on a 512-topology batch over four uneven alignments, the
+roofline of the dominant kernel and the oracle timed on this host's cores.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+GOLDEN = os.path.join(ROOT, "tests", "golden", "c2_hillclimb.json")
+TRAFFIC = os.path.join(ROOT, "profiles", "traffic_counters.json")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    with open(os.path.join(ROOT, "paper_1811_11007_amd", "csrc", "kernels.hip"), "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def c2_inputs():
+    import synth
+    g = json.load(open(GOLDEN))
+    rng = np.random.default_rng(g["seed"])
+    edges, brlen = synth.yule_tree(g["n_taxa"], rng, mean=0.05)
+    aln = synth.make_alignment(edges, brlen, g["n_taxa"], g["n_sites"], rng, alpha=0.5, n_cats=4)
+    assert aln.n_patterns == g["n_patterns"] and int(aln.tips.astype(np.int64).sum()) == g["tips_sum"], \
+        "generator output differs from the stored workload"
+    return g, aln
+
+
+def key_int(k, n):
+    W = (n + 63) // 64
+    return tuple(sum(int(row[w]) << (64 * w) for w in range(W)) for row in k)
+
+
+def c3_inputs():
+    """Four uneven alignments (27x1949, 36x1812, 50x1133, 64x1008), 128 NNI
+    walk topologies each around the generating tree: 512 topologies."""
+    import synth
+    shapes = [(27, 1949, 31), (36, 1812, 32), (50, 1133, 33), (64, 1008, 34)]
+    alns, trees, lens, idx = [], [], [], []
+    for i, (n, S, seed) in enumerate(shapes):
+        rng = np.random.default_rng(seed)
+        e, b = synth.yule_tree(n, rng, mean=0.05)
+        alns.append(synth.make_alignment(e, b, n, S, rng, alpha=0.5, n_cats=4))
+        for te, tb in synth.nni_bfs(e, b, n, 128):
+            trees.append(te)
+            lens.append(tb)
+            idx.append(i)
+    return alns, trees, np.concatenate(lens), np.array(idx, np.int32)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-extras", action="store_true", help="only the headline measurement")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build runs the batch on a single MI355X "
+              "(topologies shard across GPUs with no collective; see DESIGN.md). Use --gpus 1.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1811_11007_amd as pt
+
+    g, aln = c2_inputs()
+    n = g["n_taxa"]
+    base_e = np.asarray(g["base_edges"], np.int32)
+    base_b = np.asarray(g["base_brlen"])
+    want = {tuple(int(x) for x in nb["key"]): nb["lnl"] for nb in g["neighbours"]}
+
+    ctx = pt.Context(0)
+    A = pt.Alignment.from_synth(ctx, aln)
+    ne, nbl, _ = pt.pt_nni_neighbors(n, base_e, base_b)
+    keys = [key_int(pt.pt_topology_key(n, e), n) for e in ne]
+    assert set(keys) == set(want), "NNI neighbours differ from the stored workload"
+    ref = np.array([want[k] for k in keys])
+    T = pt.Trees(list(ne))
+    NT = T.n_trees
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream()
+
+    def run_batch(precision, steps, warmup, graphs=True, tune=True):
+        plan = pt.Plan(ctx, [A], T, pt.PT_PLAN_OPTIMIZE, precision)
+        b0 = torch.tensor(nbl.ravel(), dtype=torch.float64, device=dev)
+        b = torch.empty_like(b0)
+        lnl = torch.zeros(NT, dtype=torch.float64, device=dev)
+        ps = torch.zeros(NT, dtype=torch.int32, device=dev)
+        st = torch.zeros(NT, dtype=torch.int32, device=dev)
+        shape = None
+        with torch.cuda.stream(stream):
+            if tune:
+                shape = plan.autotune(b0)
+            plan.set_graphs(graphs)
+            ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                  for _ in range(steps)]
+
+            def step(i=None):
+                b.copy_(b0, non_blocking=True)
+                if i is not None:
+                    ev[i][0].record(stream)
+                plan.optimize(b, lnl, ps, st, stream=stream)
+                if i is not None:
+                    ev[i][1].record(stream)
+
+            for _ in range(warmup):
+                step()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for i in range(steps):
+                step(i)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+        kern_ms = float(np.mean([s.elapsed_time(e) for s, e in ev]))
+        passes = ps.cpu().numpy()
+        res = dict(ms=(t1 - t0) * 1e3 / steps, kern_ms=kern_ms, lnl=lnl.cpu().numpy(), passes=passes,
+                   status=st.cpu().numpy(), bytes=plan.traffic(pt.PT_PLAN_OPTIMIZE, passes), shape=shape)
+        plan.close()
+        return res
+
+    log("fp32 batch ...")
+    r32 = run_batch(pt.PT_FP32, args.steps, args.warmup)
+    d32 = np.abs(r32["lnl"] - ref)
+    ok = bool(np.all(d32 <= 1e-4))
+    value = NT / (r32["ms"] / 1e3)
+    achieved = r32["bytes"] / (r32["kern_ms"] / 1e3) / 1e9
+    traffic = None
+    if os.path.exists(TRAFFIC):
+        tr = json.load(open(TRAFFIC))
+        if tr.get("kernel_hash") == kernel_hash() and "optimize_c2_fp32" in tr:
+            traffic = tr["optimize_c2_fp32"]["bytes_per_launch"]
+    out = {
+        "metric": "optimized topologies/s at |dlnL|<1e-4; pruning HBM GB/s vs peak",
+        "value": round(value if ok else 0.0, 3),
+        "unit": "topologies/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(r32["ms"], 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 partials / f64 arithmetic",
+        "data": "synthetic (seeded GTR+G4 simulation; no dataset)",
+        "config": {"workload": "48 NNI neighbours of a hill-climbed 27-taxon tree, 1949 sites "
+                               "(%d patterns) GTR+G4, full branch optimisation" % aln.n_patterns,
+                   "topologies_per_step": NT, "precision": "fp32 partials + per-pattern scaling",
+                   "launch": {"block": r32["shape"][0], "items_per_thread": r32["shape"][1],
+                              "hip_graph": True}},
+        "parity": {"max_abs_dlnl_vs_oracle": float(d32.max()), "all_within_1e-4": ok,
+                   "status_converged": int(np.sum(r32["status"] == 0)),
+                   "passes_mean": float(r32["passes"].mean())},
+        "roofline": {"bound": "hbm", "kernel": "k_optimize",
+                     "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "algorithmic_bytes_per_launch": r32["bytes"], "kernel_ms": round(r32["kern_ms"], 4)},
+    }
+    if not args.no_extras:
+        log("fp64 batch ...")
+        r64 = run_batch(pt.PT_FP64, max(3, args.steps // 4), 1)
+        out["fp64"] = {"value": round(NT / (r64["ms"] / 1e3), 3), "ms_per_step": round(r64["ms"], 4),
+                       "max_rel_dlnl_vs_oracle": float(np.max(np.abs(r64["lnl"] - ref) / np.abs(ref))),
+                       "max_abs_dlnl_vs_oracle": float(np.max(np.abs(r64["lnl"] - ref)))}
+        log("per-topology path ...")
+        # plain per-topology GPU path: same kernel, one tree per plan and call, no graph
+        plans = [pt.Plan(ctx, [A], pt.Trees([ne[i]]), pt.PT_PLAN_OPTIMIZE, pt.PT_FP32) for i in range(NT)]
+        bs = [torch.tensor(nbl[i], dtype=torch.float64, device=dev) for i in range(NT)]
+        ls = [torch.zeros(1, dtype=torch.float64, device=dev) for _ in range(NT)]
+        for rep in range(2):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for i in range(NT):
+                bs[i].copy_(torch.tensor(nbl[i], dtype=torch.float64))
+                plans[i].optimize(bs[i], ls[i], stream=stream)
+                stream.synchronize()
+            t1 = time.perf_counter()
+        pl_l = np.array([float(x.item()) for x in ls])
+        out["per_topology_path"] = {"value": round(NT / (t1 - t0), 3), "unit": "topologies/s",
+                                    "max_abs_dlnl_vs_oracle": float(np.max(np.abs(pl_l - ref)))}
+        out["batched_over_per_topology"] = round(value / out["per_topology_path"]["value"], 2)
+        for p_ in plans:
+            p_.close()
+
+        log("pruning on 512 topologies ...")
+        alns3, trees3, lens3, idx3 = c3_inputs()
+        A3 = [pt.Alignment.from_synth(ctx, a) for a in alns3]
+        T3 = pt.Trees(trees3, idx3)
+        plan3 = pt.Plan(ctx, A3, T3, pt.PT_PLAN_LOGLIK, pt.PT_FP32)
+        b3 = torch.tensor(lens3, dtype=torch.float64, device=dev)
+        l3 = torch.zeros(T3.n_trees, dtype=torch.float64, device=dev)
+        with torch.cuda.stream(stream):
+            plan3.set_graphs(True)
+            for _ in range(3):
+                plan3.loglik(b3, l3, stream=stream)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            reps = 20
+            e0.record(stream)
+            for _ in range(reps):
+                plan3.loglik(b3, l3, stream=stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+        ms3 = e0.elapsed_time(e1) / reps
+        by3 = plan3.traffic(pt.PT_PLAN_LOGLIK)
+        out["pruning"] = {"workload": "512 topologies over 27x1949, 36x1812, 50x1133, 64x1008 GTR+G4, FP32",
+                          "ms_per_call": round(ms3, 4), "algorithmic_bytes": by3,
+                          "achieved_GBs": round(by3 / (ms3 / 1e3) / 1e9, 1),
+                          "frac_of_peak": round(by3 / (ms3 / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                          "note": "graph of k_pmat + k_tiles + k_reduce"}
+        plan3.close()
+
+    if not args.no_cpu:
+        log("oracle cpu baseline ...")
+        from oracle import core as oc
+        D = oc.Data.from_alignment(aln)
+        t0 = time.perf_counter()
+        done = 0
+        while done < len(ne) and (time.perf_counter() - t0) < 15.0:
+            oc.optimize(D, ne[done], nbl[done])
+            done += 1
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": round(done / dt, 4), "unit": "topologies/s", "cores": 1,
+                               "kind": "oracle",
+                               "sample": "first %d of the 48 neighbours, FP64 oracle full optimisation "
+                                         "(its own tolerances), single thread, %.1f s" % (done, dt),
+                               "host_cpus": os.cpu_count()}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -144,9 +144,13 @@ pt_status pt_batch_branch_grad(pt_ctx *ctx, pt_aln *const *alns, int32_t n_alns,
  * partial updates and edge steps, device descriptors, partial buffers) so it
  * can be run many times on device-resident lengths.  kinds is a bitwise OR
  * of PT_PLAN_*.  opt_mask as in pt_batch_optimize_branches (fixed per plan).
- * Plan calls enqueue on `stream` (a hipStream_t; NULL = the context's stream)
+ * Plan calls enqueue on `stream` (a hipStream_t; NULL = the null stream)
  * and return without waiting.  With graphs enabled (pt_plan_set_graphs), each
- * distinct argument set is captured once into a HIP graph and replayed. */
+ * distinct argument set on a non-NULL stream is captured once into a HIP
+ * graph and replayed.  Every layout of a plan uses the category count of the
+ * widest alignment its trees use (padded to 1, 2, 4 or 8), so a plan mixing
+ * category counts can exceed the per-tree LDS limit (PT_EUNSUPPORTED); the
+ * host-pointer batch calls split batches by category count themselves. */
 #define PT_PLAN_LOGLIK 1
 #define PT_PLAN_OPTIMIZE 2
 #define PT_PLAN_GRAD 4
@@ -173,6 +177,23 @@ pt_status pt_plan_grad(pt_plan *plan, const double *d_brlen, double *d_lnl,
  * chosen threads per block and items per thread to *block, *items (NULL ok). */
 pt_status pt_plan_autotune(pt_plan *plan, const double *d_brlen, const pt_opt *opt,
                            int32_t *block, int32_t *items);
+
+/* Algorithmic device-memory bytes one run of `kind` moves: every partial,
+ * scaler, tip code and weight its programs read or write once per use
+ * (Newton iterations and transition matrices add none).  For
+ * PT_PLAN_OPTIMIZE, passes[n_trees] (host; NULL = 1) gives the passes each
+ * tree ran.  Used to express kernel throughput against the memory
+ * bandwidth roofline. */
+pt_status pt_plan_traffic(const pt_plan *plan, int32_t kind, const int32_t *passes,
+                          double *bytes_out);
+
+/* Phase profile of the optimisation kernel: with d_counters (device
+ * int64[n_trees][8]) set, every later pt_plan_optimize writes per tree:
+ * passes, edge steps, Newton iterations, partial updates, then shader-clock
+ * cycles spent in updates, in building eigenbasis tables, in Newton
+ * iterations, and in total.  NULL turns it off.  Costs a few clock reads
+ * per step; meant for tuning, not for timed runs. */
+pt_status pt_plan_set_profile(pt_plan *plan, void *d_counters);
 
 /* Number of trees, total edges and device bytes held by the plan. */
 pt_status pt_plan_info(const pt_plan *plan, int32_t *n_trees, int64_t *n_edges,

@@ -23,7 +23,7 @@ EXPORTS = [
     "pt_last_error", "pt_ctx_create", "pt_ctx_destroy", "pt_aln_create", "pt_aln_destroy",
     "pt_opt_default", "pt_batch_loglik", "pt_batch_optimize_branches", "pt_batch_branch_grad",
     "pt_plan_create", "pt_plan_destroy", "pt_plan_set_graphs", "pt_plan_loglik",
-    "pt_plan_optimize", "pt_plan_grad", "pt_plan_autotune", "pt_plan_info",
+    "pt_plan_optimize", "pt_plan_grad", "pt_plan_autotune", "pt_plan_traffic", "pt_plan_set_profile", "pt_plan_info",
     "pt_model_info", "pt_tree_check", "pt_nni_neighbors", "pt_topology_key",
 ]
 
@@ -61,6 +61,13 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise RuntimeError("libpt.so is not built: run paper_1811_11007_amd/build.py "
                                "(or __graft_entry__.build())")
+        # One HIP runtime per process: when torch is present its bundled
+        # runtime is loaded first and libpt binds to it by soname, so device
+        # pointers and streams from torch are valid in the library's calls.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = ctypes.CDLL(LIB_PATH)
         vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
         P = ctypes.POINTER
@@ -86,6 +93,8 @@ def lib():
         L.pt_plan_grad.argtypes = [vp, vp, vp, vp, vp, vp]
         L.pt_plan_autotune.argtypes = [vp, vp, P(pt_opt), P(i32), P(i32)]
         L.pt_plan_info.argtypes = [vp, P(i32), P(i64), P(i64)]
+        L.pt_plan_traffic.argtypes = [vp, i32, vp, P(ctypes.c_double)]
+        L.pt_plan_set_profile.argtypes = [vp, vp]
         L.pt_model_info.argtypes = [P(pt_model), vp, vp, vp, vp]
         L.pt_tree_check.argtypes = [i32, vp]
         L.pt_nni_neighbors.argtypes = [i32, vp, vp, vp, vp, vp]
@@ -311,6 +320,18 @@ class Plan:
         check(lib().pt_plan_autotune(self.h, ctypes.c_void_p(d_brlen.data_ptr()),
                                      ctypes.byref(opt) if opt else None, ctypes.byref(b), ctypes.byref(i)))
         return b.value, i.value
+
+    def traffic(self, kind, passes=None):
+        """Algorithmic device bytes one run of `kind` moves."""
+        ps = None if passes is None else np.ascontiguousarray(passes, dtype=np.int32)
+        out = ctypes.c_double()
+        check(lib().pt_plan_traffic(self.h, kind, _ptr(ps), ctypes.byref(out)))
+        return out.value
+
+    def set_profile(self, d_counters):
+        """d_counters: device int64 tensor [n_trees, 8], or None to stop."""
+        check(lib().pt_plan_set_profile(
+            self.h, None if d_counters is None else ctypes.c_void_p(d_counters.data_ptr())))
 
     def info(self):
         n, e, by = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int64()

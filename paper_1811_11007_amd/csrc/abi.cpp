@@ -44,7 +44,7 @@ pt_status fail(pt_status st, const std::string &msg) {
 
 // LDS the kernels may use for the per-tree transition matrix cache.
 constexpr size_t kLdsBudget = 64 * 1024;
-constexpr int kMaxOptItems = 1024 * 16;
+constexpr int kMaxOptPatterns = 512 * 64;
 
 int64_t arena_cap() {
     const char *s = std::getenv("PT_ARENA_CAP_BYTES");
@@ -59,9 +59,11 @@ int64_t arena_cap() {
 struct pt_ctx {
     int device = 0;
     int n_cu = 0;
+    size_t lds_per_block = 65536;
     hipStream_t stream = nullptr;
-    // tuned launch shape per (precision, Kp, item capacity)
-    std::map<std::tuple<int, int, int>, std::pair<int, int>> tuned;
+    // tuned threads per block of the optimisation kernel, per (precision,
+    // padded categories, largest item count)
+    std::map<std::tuple<int, int, int>, int> tuned;
 };
 
 struct pt_aln {
@@ -77,7 +79,7 @@ struct pt_plan {
     int precision = 0, kinds = 0;
     int n_trees = 0;
     int64_t n_edges = 0;
-    int max_items = 0, max_E = 0, n_tiles = 0, kp = 1;
+    int max_P = 0, max_E = 0, n_tiles = 0, kp = 1;
     std::vector<int> tree_E;
     AlnDev *d_alns = nullptr;
     Op *d_ops = nullptr;
@@ -87,11 +89,19 @@ struct pt_plan {
     uint16_t *d_cnt = nullptr;
     double *d_pmat = nullptr, *d_part = nullptr, *d_scratch = nullptr;
     size_t lds_tiles = 0, lds_opt = 0;
-    int opt_block = 0, opt_items = 0, opt_grid = 0;
+    int opt_block = 0, opt_items = 0, opt_grid = 0, pm_doubles = 0;
+    bool opt_tab_lds = true;
+    void *d_tab = nullptr;
+    size_t tab_bytes = 0;
+    long long *d_prof = nullptr;
     int64_t device_bytes = 0;
     bool graphs = false;
     std::map<std::vector<uint64_t>, hipGraphExec_t> execs;
     std::vector<void *> allocs;
+    // host copies for traffic accounting
+    std::vector<Op> ops_h;
+    std::vector<TreeDev> tll_h, tgr_h, top_h;
+    std::vector<AlnDev> alns_h;
 };
 
 namespace {
@@ -180,33 +190,58 @@ int64_t tree_bytes(int n, const AlnDev &a, int precision, int kinds) {
     int64_t b = (int64_t)slots * items * 4 * store_bytes(precision) + (int64_t)slots * a.P * 2;
     b += (int64_t)E * a.Kp * 16 * 8 + 64 * E + 256;
     if (kinds & (PT_PLAN_LOGLIK | PT_PLAN_GRAD)) {
-        int64_t tiles = (items + pt::kTileBlock * pt::kTileItems - 1) / (pt::kTileBlock * pt::kTileItems);
+        int64_t tiles = (a.P + pt::kTileBlock * pt::kTileItems - 1) / (pt::kTileBlock * pt::kTileItems);
         b += tiles * (int64_t)E * 3 * 8 + tiles * 4;
     }
     return b;
 }
 
-void pick_shape(pt_plan *pl) {
-    static const int blocks[3] = {256, 512, 1024};
-    static const int items[6] = {1, 2, 4, 8, 12, 16};
-    int best_b = 0, best_i = 0;
-    long best_cap = 0;
-    for (int ii : items)
-        for (int bb : blocks) {
-            if (!pt::optimize_shape_supported(bb, ii)) continue;
-            long cap = (long)bb * ii;
-            if (cap < pl->max_items) continue;
-            if (!best_b || cap < best_cap || (cap == best_cap && ii < best_i)) {
-                best_b = bb; best_i = ii; best_cap = cap;
-            }
+// Static LDS of the optimisation kernel at 512 threads (reduction buffers,
+// per-wave exponential tables, model, counter), rounded up.
+constexpr size_t kOptStaticLds = 8192;
+
+// Sets the optimisation launch shape for `block` threads per block: patterns
+// per thread, where the eigenbasis table lives (LDS when it fits, else a
+// per-block global buffer), dynamic LDS, grid.  Refuses shapes whose kernel
+// needs private (spill) memory.
+pt_status configure_shape(pt_plan *pl, int block) {
+    const int ni = (pl->max_P + block - 1) / block;
+    if (!pt::optimize_shape_supported(block, ni))
+        return fail(PT_EUNSUPPORTED, "patterns x padded categories too large for the optimisation kernel");
+    const size_t esz = store_bytes(pl->precision);
+    const size_t tab_lds = (size_t)block * ni * pl->kp * 4 * esz + (size_t)block * ni * 8;
+    const size_t pm_bytes = (size_t)pl->pm_doubles * 8;
+    const bool lds_ok = pm_bytes + tab_lds + kOptStaticLds <= pl->ctx->lds_per_block;
+    if (pt::optimize_spill_bytes(pl->precision, block, pl->kp, lds_ok) != 0)
+        return fail(PT_EUNSUPPORTED, "optimisation kernel shape needs register spills");
+    const size_t lds = pm_bytes + (lds_ok ? tab_lds : 0);
+    int per_cu = pt::optimize_blocks_per_cu(pl->precision, block, pl->kp, lds_ok, lds);
+    if (per_cu < 1) return fail(PT_EUNSUPPORTED, "optimisation kernel does not fit on a compute unit");
+    const int grid = (int)std::max(1L, std::min<long>(pl->n_trees, (long)per_cu * std::max(1, pl->ctx->n_cu)));
+    if (!lds_ok) {
+        size_t need = (size_t)grid * tab_lds;
+        if (need > pl->tab_bytes) {
+            void *p = nullptr;
+            hipError_t e = hipMalloc(&p, need);
+            if (e != hipSuccess) return fail(PT_ENOMEM, std::string("hipMalloc(eigenbasis tables): ") + hipGetErrorString(e));
+            pl->allocs.push_back(p);
+            pl->device_bytes += (int64_t)need;
+            pl->d_tab = p;
+            pl->tab_bytes = need;
         }
-    pl->opt_block = best_b;
-    pl->opt_items = best_i;
+    }
+    pl->opt_block = block;
+    pl->opt_items = ni;
+    pl->opt_tab_lds = lds_ok;
+    pl->lds_opt = lds;
+    pl->opt_grid = grid;
+    return PT_OK;
 }
 
-int kp_of_plan(pt_aln *const *alns, int n_alns) {
+// Padded category count of a plan: that of the widest alignment its trees use.
+int kp_of_plan(pt_aln *const *alns, const pt_trees *trees) {
     int kp = 1;
-    for (int i = 0; i < n_alns; ++i) kp = std::max(kp, alns[i]->desc.Kp);
+    for (int b = 0; b < trees->n_trees; ++b) kp = std::max(kp, alns[trees->aln_index[b]]->desc.Kp);
     return kp;
 }
 
@@ -236,7 +271,9 @@ pt_status plan_build(pt_ctx *ctx, pt_aln *const *alns, int32_t n_alns, const pt_
     std::vector<double> cost(B);
     int64_t clv_off = 0, cnt_off = 0, pm_off = 0;
     int tiles = 0;
-    const int64_t tile_items = (int64_t)pt::kTileBlock * pt::kTileItems;
+    const int64_t tile_pats = (int64_t)pt::kTileBlock * pt::kTileItems;
+    const int kp = kp_of_plan(alns, trees);
+    pl->kp = kp;
     std::string err;
     for (int b = 0; b < B; ++b) {
         const pt_aln *al = alns[trees->aln_index[b]];
@@ -246,14 +283,13 @@ pt_status plan_build(pt_ctx *ctx, pt_aln *const *alns, int32_t n_alns, const pt_
         st = pt::build_tree(ntx[b], ed, t, err);
         if (st) return fail(st, "tree " + std::to_string(b) + ": " + err);
         const int E = t.n_edges;
-        if ((size_t)E * ad.Kp * 16 * 8 + (size_t)E * 8 > kLdsBudget)
+        if ((size_t)E * kp * 16 * 8 + (size_t)E * 8 > kLdsBudget)
             return fail(PT_EUNSUPPORTED, "tree " + std::to_string(b) + ": (2n-3) * padded categories exceeds the 64 KiB "
                                          "transition-matrix cache (at most 504 edge-categories)");
-        const int items = ad.P * ad.Kp;
-        if ((kinds & PT_PLAN_OPTIMIZE) && items > kMaxOptItems)
-            return fail(PT_EUNSUPPORTED, "tree " + std::to_string(b) + ": patterns x padded categories exceeds 16384 "
+        if ((kinds & PT_PLAN_OPTIMIZE) && ad.P > kMaxOptPatterns)
+            return fail(PT_EUNSUPPORTED, "tree " + std::to_string(b) + ": more than 32768 patterns "
                                          "for branch optimisation");
-        pl->max_items = std::max(pl->max_items, items);
+        pl->max_P = std::max(pl->max_P, ad.P);
         pl->max_E = std::max(pl->max_E, E);
         pl->tree_E.push_back(E);
         TreeDev base{};
@@ -264,11 +300,11 @@ pt_status plan_build(pt_ctx *ctx, pt_aln *const *alns, int32_t n_alns, const pt_
         base.cnt_off = cnt_off;
         base.edge_off = trees->edge_offset[b];
         base.pm_off = pm_off;
-        base.n_tiles = (int)((items + tile_items - 1) / tile_items);
+        base.n_tiles = (int)((ad.P + tile_pats - 1) / tile_pats);
         base.tile_begin = tiles;
-        clv_off += (int64_t)t.n_slots() * items * 4;
+        clv_off += (int64_t)t.n_slots() * kp * ad.P * 4;
         cnt_off += (int64_t)t.n_slots() * ad.P;
-        pm_off += (int64_t)E * ad.Kp * 16;
+        pm_off += (int64_t)E * kp * 16;
         for (int64_t i = 0; i < E; ++i) edge_tree[base.edge_off + i] = b;
         tll[b] = tgr[b] = top[b] = base;
         if (kinds & (PT_PLAN_LOGLIK | PT_PLAN_GRAD)) {
@@ -302,10 +338,22 @@ pt_status plan_build(pt_ctx *ctx, pt_aln *const *alns, int32_t n_alns, const pt_
             top[b].op_steady = (int32_t)ops.size();
             top[b].n_steady = (int32_t)p2.size();
             ops.insert(ops.end(), p2.begin(), p2.end());
-            cost[b] = (double)items * (double)(p2.size() + 1);
+            if (precision == PT_FP32) {
+                std::vector<Op> p3;
+                pt::compile_loglik_dense(t, p3);
+                top[b].op_final = (int32_t)ops.size();
+                top[b].n_final = (int32_t)p3.size();
+                ops.insert(ops.end(), p3.begin(), p3.end());
+            }
+            cost[b] = (double)ad.P * ad.K * (double)(p2.size() + 1);
         }
     }
     pl->n_tiles = tiles;
+    pl->ops_h = ops;
+    pl->tll_h = tll;
+    pl->tgr_h = tgr;
+    pl->top_h = top;
+    for (int i = 0; i < n_alns; ++i) pl->alns_h.push_back(alns[i]->desc);
 
     // arena cap
     int64_t need = clv_off * (int64_t)store_bytes(precision) + cnt_off * 2 + pm_off * 8 +
@@ -355,22 +403,22 @@ pt_status plan_build(pt_ctx *ctx, pt_aln *const *alns, int32_t n_alns, const pt_
     if ((st = dev_alloc(pl.get(), &pl->d_pmat, (size_t)pm_off * 8))) return st;
     PT_HIP(hipSetDevice(dev_prev));
 
-    pl->kp = kp_of_plan(alns, n_alns);
     pl->lds_tiles = 0;
     for (int b = 0; b < B; ++b) {
         const AlnDev &a2 = alns[trees->aln_index[b]]->desc;
-        pl->lds_tiles = std::max(pl->lds_tiles, (size_t)pl->tree_E[b] * a2.Kp * 16 * 8);
-        pl->lds_opt = std::max(pl->lds_opt, (size_t)pl->tree_E[b] * (a2.Kp * 16 + 1) * 8);
+        (void)a2;
+        pl->lds_tiles = std::max(pl->lds_tiles, (size_t)pl->tree_E[b] * kp * 16 * 8);
+        pl->pm_doubles = std::max(pl->pm_doubles, pl->tree_E[b] * (kp * 16 + 1));
     }
+    pl->pm_doubles = (pl->pm_doubles + 3) / 4 * 4;  // 32-byte aligned table rows after it
     if (kinds & PT_PLAN_OPTIMIZE) {
-        auto it = ctx->tuned.find(std::make_tuple(precision, pl->kp, pl->max_items));
-        if (it != ctx->tuned.end()) {
-            pl->opt_block = it->second.first;
-            pl->opt_items = it->second.second;
-        } else {
-            pick_shape(pl.get());
-        }
-        if (!pl->opt_block) return fail(PT_EUNSUPPORTED, "no launch shape covers the pattern count");
+        auto it = ctx->tuned.find(std::make_tuple(precision, pl->kp, pl->max_P));
+        st = PT_EUNSUPPORTED;
+        if (it != ctx->tuned.end()) st = configure_shape(pl.get(), it->second);
+        // default: the widest block that needs no spills
+        for (int bs : {512, 256, 1024})
+            if (st) st = configure_shape(pl.get(), bs);
+        if (st) return st;
     }
     *out = pl.release();
     return PT_OK;
@@ -393,14 +441,8 @@ pt::BatchArgs batch_args(const pt_plan *pl, const TreeDev *trees, int part_cols)
     a.n_tiles = pl->n_tiles;
     a.n_edges = pl->n_edges;
     a.part_cols = part_cols;
+    a.kp = pl->kp;
     return a;
-}
-
-int opt_grid(pt_plan *pl) {
-    int per_cu = pt::optimize_blocks_per_cu(pl->precision, pl->opt_block, pl->opt_items, pl->lds_opt);
-    if (per_cu < 1) per_cu = 1;
-    long cap = (long)per_cu * std::max(1, pl->ctx->n_cu);
-    return (int)std::max(1L, std::min<long>(pl->n_trees, cap));
 }
 
 // Enqueue the kernels of one plan call.
@@ -412,16 +454,17 @@ pt_status enqueue(pt_plan *pl, int kind, const double *brlen_c, double *brlen, c
         const bool g = kind == PT_PLAN_GRAD;
         pt::BatchArgs a = batch_args(pl, g ? pl->d_trees_gr : pl->d_trees_ll, g ? std::max(1, pl->max_E) : 1);
         if ((e = pt::launch_pmat(a, brlen_c, s)) != hipSuccess) goto bad;
-        if ((e = pt::launch_tiles(pl->precision, g, a, brlen_c, pl->lds_tiles, s)) != hipSuccess) goto bad;
+        if ((e = pt::launch_tiles(pl->precision, pl->kp, a, brlen_c, pl->lds_tiles, s)) != hipSuccess) goto bad;
         if ((e = pt::launch_reduce(g, a, lnl, grad, hess, s)) != hipSuccess) goto bad;
         return PT_OK;
     }
     {
         pt::BatchArgs a = batch_args(pl, pl->d_trees_opt, 1);
+        a.tab = pl->d_tab;
+        a.prof = pl->d_prof;
         if ((e = pt::launch_fill_i32(pl->d_queue, 0, 1, s)) != hipSuccess) goto bad;
-        if (!pl->opt_grid) pl->opt_grid = opt_grid(pl);
-        if ((e = pt::launch_optimize(pl->precision, pl->opt_block, pl->opt_items, pl->opt_grid, a, brlen, *op, lnl,
-                                     passes, status, pl->lds_opt, s)) != hipSuccess)
+        if ((e = pt::launch_optimize(pl->precision, pl->opt_block, pl->kp, pl->opt_items, pl->opt_tab_lds, pl->pm_doubles,
+                                     pl->opt_grid, a, brlen, *op, lnl, passes, status, pl->lds_opt, s)) != hipSuccess)
             goto bad;
         return PT_OK;
     }
@@ -459,32 +502,39 @@ pt_status run(pt_plan *pl, int kind, const double *brlen_c, double *brlen, const
     return PT_OK;
 }
 
-// Split trees [0, n) into consecutive chunks whose plans fit the arena cap.
-pt_status chunks_for(pt_aln *const *alns, const pt_trees *trees, const std::vector<int> &ntx, int precision,
-                     int kinds, std::vector<std::pair<int, int>> &out) {
+// Groups the trees of a host-pointer batch into chunks: one group per padded
+// category count (every layout of a plan uses its widest alignment's), each
+// group split so that no chunk's plan exceeds the arena cap.
+pt_status make_chunks(pt_aln *const *alns, const pt_trees *trees, const std::vector<int> &ntx, int precision,
+                      int kinds, std::vector<std::vector<int>> &out) {
     const int64_t cap = arena_cap();
     const int B = trees->n_trees;
-    if (cap <= 0) {
-        out.push_back({0, B});
-        return PT_OK;
-    }
-    int64_t used = 0;
-    int start = 0;
-    for (int b = 0; b < B; ++b) {
-        int64_t need = tree_bytes(ntx[b], alns[trees->aln_index[b]]->desc, precision, kinds) + 4096;
-        if (need > cap) return fail(PT_ENOMEM, "tree " + std::to_string(b) + " alone exceeds PT_ARENA_CAP_BYTES");
-        if (used + need > cap && b > start) {
-            out.push_back({start, b});
-            start = b;
-            used = 0;
+    for (int kp : {1, 2, 4, 8}) {
+        std::vector<int> cur;
+        int64_t used = 0;
+        for (int b = 0; b < B; ++b) {
+            const AlnDev &ad = alns[trees->aln_index[b]]->desc;
+            if (ad.Kp != kp) continue;
+            if (cap > 0) {
+                int64_t need = tree_bytes(ntx[b], ad, precision, kinds) + 4096;
+                if (need > cap) return fail(PT_ENOMEM, "tree " + std::to_string(b) + " alone exceeds PT_ARENA_CAP_BYTES");
+                if (used + need > cap && !cur.empty()) {
+                    out.push_back(cur);
+                    cur.clear();
+                    used = 0;
+                }
+                used += need;
+            }
+            cur.push_back(b);
         }
-        used += need;
+        if (!cur.empty()) out.push_back(cur);
     }
-    out.push_back({start, B});
     return PT_OK;
 }
 
-// Host-pointer batch driver shared by the three batch calls.
+// Host-pointer batch driver shared by the three batch calls: validate, split
+// into chunks, run each chunk as its own plan, scatter results; outputs are
+// written only after every chunk has succeeded.
 pt_status host_batch(pt_ctx *ctx, pt_aln *const *alns, int32_t n_alns, const pt_trees *trees, double *brlen_io,
                      const double *brlen_in, const uint8_t *mask, const pt_opt *opt, int precision, int kind,
                      double *lnl_out, int32_t *passes_out, int32_t *status_out, double *grad_out, double *hess_out) {
@@ -498,39 +548,44 @@ pt_status host_batch(pt_ctx *ctx, pt_aln *const *alns, int32_t n_alns, const pt_
     if ((st = check_lengths(lens, NE))) return st;
     if (B > 0 && !lnl_out) return fail(PT_EINVAL, "lnl_out is NULL");
     if (kind == PT_PLAN_GRAD && NE > 0 && !grad_out) return fail(PT_EINVAL, "grad_out is NULL");
+    if (mask)
+        for (int64_t i = 0; i < NE; ++i)
+            if (mask[i] > 1) return fail(PT_EINVAL, "opt_mask entries must be 0 or 1");
     pt_opt o;
     if (kind == PT_PLAN_OPTIMIZE) {
         if (opt) o = *opt; else pt_opt_default(precision, &o);
         if ((st = check_opt(o))) return st;
     }
-    std::vector<std::pair<int, int>> parts;
-    if ((st = chunks_for(alns, trees, ntx, precision, kind, parts))) return st;
-    // validate every chunk before any device work
-    std::vector<std::unique_ptr<pt_plan, void (*)(pt_plan *)>> plans;
-    std::vector<pt_trees> subs;
-    for (auto &pr : parts) {
-        pt_trees sub;
-        sub.n_trees = pr.second - pr.first;
-        sub.aln_index = trees->aln_index + pr.first;
-        sub.edges = trees->edges + 2 * trees->edge_offset[pr.first];
-        subs.push_back(sub);
-    }
-    std::vector<std::vector<int64_t>> offs(parts.size());
-    for (size_t c = 0; c < parts.size(); ++c) {
-        const auto &pr = parts[c];
-        offs[c].resize(pr.second - pr.first + 1);
-        for (int b = pr.first; b <= pr.second; ++b) offs[c][b - pr.first] = trees->edge_offset[b] - trees->edge_offset[pr.first];
-        subs[c].edge_offset = offs[c].data();
-    }
-    // outputs are written only after every chunk has succeeded
+    std::vector<std::vector<int>> chunks;
+    if ((st = make_chunks(alns, trees, ntx, precision, kind, chunks))) return st;
+
     std::vector<double> lnl(B), lens_out(lens, lens + NE), grad(kind == PT_PLAN_GRAD ? NE : 0),
         hess(kind == PT_PLAN_GRAD && hess_out ? NE : 0);
     std::vector<int32_t> passes(B), status(B);
-    for (size_t c = 0; c < parts.size(); ++c) {
-        const int b0 = parts[c].first, nb = parts[c].second - parts[c].first;
-        const int64_t e0 = trees->edge_offset[b0], ne = trees->edge_offset[parts[c].second] - e0;
+    for (const std::vector<int> &ch : chunks) {
+        const int nb = (int)ch.size();
+        // contiguous copies of the chunk's trees
+        std::vector<int32_t> ai(nb), ed;
+        std::vector<int64_t> off(nb + 1, 0);
+        std::vector<double> cl;
+        std::vector<uint8_t> cm;
+        for (int i = 0; i < nb; ++i) {
+            const int b = ch[i];
+            const int64_t e0 = trees->edge_offset[b], e1 = trees->edge_offset[b + 1];
+            ai[i] = trees->aln_index[b];
+            off[i + 1] = off[i] + (e1 - e0);
+            ed.insert(ed.end(), trees->edges + 2 * e0, trees->edges + 2 * e1);
+            cl.insert(cl.end(), lens + e0, lens + e1);
+            if (mask) cm.insert(cm.end(), mask + e0, mask + e1);
+        }
+        const int64_t ne = off[nb];
+        pt_trees sub;
+        sub.n_trees = nb;
+        sub.aln_index = ai.data();
+        sub.edge_offset = off.data();
+        sub.edges = ed.data();
         pt_plan *raw = nullptr;
-        st = plan_build(ctx, alns, n_alns, &subs[c], mask ? mask + e0 : nullptr, precision, kind, &raw);
+        st = plan_build(ctx, alns, n_alns, &sub, mask ? cm.data() : nullptr, precision, kind, &raw);
         if (st) return st;
         std::unique_ptr<pt_plan, void (*)(pt_plan *)> pl(raw, free_plan);
         PT_HIP(hipSetDevice(ctx->device));
@@ -538,7 +593,7 @@ pt_status host_batch(pt_ctx *ctx, pt_aln *const *alns, int32_t n_alns, const pt_
         int32_t *d_ps = nullptr, *d_st = nullptr;
         if ((st = dev_alloc(pl.get(), &d_len, sizeof(double) * std::max<int64_t>(1, ne)))) return st;
         if ((st = dev_alloc(pl.get(), &d_lnl, sizeof(double) * std::max(1, nb)))) return st;
-        if (ne) PT_HIP(hipMemcpyAsync(d_len, lens + e0, sizeof(double) * ne, hipMemcpyHostToDevice, ctx->stream));
+        if (ne) PT_HIP(hipMemcpyAsync(d_len, cl.data(), sizeof(double) * ne, hipMemcpyHostToDevice, ctx->stream));
         pt::OptParams op{};
         if (kind == PT_PLAN_OPTIMIZE) {
             op = to_params(o);
@@ -553,17 +608,34 @@ pt_status host_batch(pt_ctx *ctx, pt_aln *const *alns, int32_t n_alns, const pt_
             st = enqueue(pl.get(), kind, d_len, nullptr, nullptr, d_lnl, nullptr, nullptr, nullptr, nullptr, ctx->stream);
         }
         if (st) return st;
-        if (nb) PT_HIP(hipMemcpyAsync(lnl.data() + b0, d_lnl, sizeof(double) * nb, hipMemcpyDeviceToHost, ctx->stream));
-        if (kind == PT_PLAN_OPTIMIZE && nb) {
-            PT_HIP(hipMemcpyAsync(lens_out.data() + e0, d_len, sizeof(double) * ne, hipMemcpyDeviceToHost, ctx->stream));
-            PT_HIP(hipMemcpyAsync(passes.data() + b0, d_ps, sizeof(int32_t) * nb, hipMemcpyDeviceToHost, ctx->stream));
-            PT_HIP(hipMemcpyAsync(status.data() + b0, d_st, sizeof(int32_t) * nb, hipMemcpyDeviceToHost, ctx->stream));
+        std::vector<double> r_lnl(nb), r_len(kind == PT_PLAN_OPTIMIZE ? ne : 0), r_g(kind == PT_PLAN_GRAD ? ne : 0),
+            r_h(d_h ? ne : 0);
+        std::vector<int32_t> r_ps(nb), r_st(nb);
+        PT_HIP(hipMemcpyAsync(r_lnl.data(), d_lnl, sizeof(double) * nb, hipMemcpyDeviceToHost, ctx->stream));
+        if (kind == PT_PLAN_OPTIMIZE) {
+            if (ne) PT_HIP(hipMemcpyAsync(r_len.data(), d_len, sizeof(double) * ne, hipMemcpyDeviceToHost, ctx->stream));
+            PT_HIP(hipMemcpyAsync(r_ps.data(), d_ps, sizeof(int32_t) * nb, hipMemcpyDeviceToHost, ctx->stream));
+            PT_HIP(hipMemcpyAsync(r_st.data(), d_st, sizeof(int32_t) * nb, hipMemcpyDeviceToHost, ctx->stream));
         }
         if (kind == PT_PLAN_GRAD && ne) {
-            PT_HIP(hipMemcpyAsync(grad.data() + e0, d_g, sizeof(double) * ne, hipMemcpyDeviceToHost, ctx->stream));
-            if (d_h) PT_HIP(hipMemcpyAsync(hess.data() + e0, d_h, sizeof(double) * ne, hipMemcpyDeviceToHost, ctx->stream));
+            PT_HIP(hipMemcpyAsync(r_g.data(), d_g, sizeof(double) * ne, hipMemcpyDeviceToHost, ctx->stream));
+            if (d_h) PT_HIP(hipMemcpyAsync(r_h.data(), d_h, sizeof(double) * ne, hipMemcpyDeviceToHost, ctx->stream));
         }
         PT_HIP(hipStreamSynchronize(ctx->stream));
+        for (int i = 0; i < nb; ++i) {
+            const int b = ch[i];
+            const int64_t e0 = trees->edge_offset[b];
+            lnl[b] = r_lnl[i];
+            passes[b] = r_ps[i];
+            status[b] = r_st[i];
+            for (int64_t x = off[i]; x < off[i + 1]; ++x) {
+                if (kind == PT_PLAN_OPTIMIZE) lens_out[e0 + x - off[i]] = r_len[x];
+                if (kind == PT_PLAN_GRAD) {
+                    grad[e0 + x - off[i]] = r_g[x];
+                    if (d_h) hess[e0 + x - off[i]] = r_h[x];
+                }
+            }
+        }
     }
     std::copy(lnl.begin(), lnl.end(), lnl_out);
     if (kind == PT_PLAN_OPTIMIZE) {
@@ -599,6 +671,7 @@ pt_status pt_ctx_create(int32_t device, pt_ctx **out) {
         return fail(PT_EDEVICE, std::string("device set-up: ") + hipGetErrorString(e));
     }
     c->n_cu = prop.multiProcessorCount;
+    c->lds_per_block = prop.sharedMemPerBlock;
     *out = c;
     return PT_OK;
 }
@@ -745,55 +818,79 @@ pt_status pt_plan_autotune(pt_plan *plan, const double *d_brlen, const pt_opt *o
     hipStream_t s = plan->ctx->stream;
     double *d_lnl = nullptr;
     if ((st = dev_alloc(plan, &d_lnl, sizeof(double) * plan->n_trees))) return st;
-    static const int blocks[3] = {256, 512, 1024};
-    static const int nis[6] = {1, 2, 4, 8, 12, 16};
-    int best_b = plan->opt_block, best_i = plan->opt_items;
+    int best_b = plan->opt_block;
     float best_ms = 1e30f;
     hipEvent_t e0, e1;
     PT_HIP(hipEventCreate(&e0));
     PT_HIP(hipEventCreate(&e1));
     const size_t nb = sizeof(double) * plan->n_edges;
-    long min_cap = 0;
-    for (int ni : nis)
-        for (int bs : blocks)
-            if ((long)bs * ni >= plan->max_items && (!min_cap || (long)bs * ni < min_cap)) min_cap = (long)bs * ni;
-    for (int ni : nis)
-        for (int bs : blocks) {
-            long cap = (long)bs * ni;
-            if (!pt::optimize_shape_supported(bs, ni) || cap < plan->max_items || cap > 4 * min_cap) continue;
-            if (pt::optimize_blocks_per_cu(plan->precision, bs, ni, plan->lds_opt) < 1) continue;
-            plan->opt_block = bs;
-            plan->opt_items = ni;
-            plan->opt_grid = 0;
-            float ms_best_trial = 1e30f;
-            for (int rep = 0; rep < 2; ++rep) {
-                PT_HIP(hipMemcpyAsync(plan->d_scratch, d_brlen, nb, hipMemcpyDeviceToDevice, s));
-                PT_HIP(hipEventRecord(e0, s));
-                st = enqueue(plan, PT_PLAN_OPTIMIZE, nullptr, plan->d_scratch, &p, d_lnl, nullptr, nullptr, nullptr,
-                             nullptr, s);
-                if (st) return st;
-                PT_HIP(hipEventRecord(e1, s));
-                PT_HIP(hipEventSynchronize(e1));
-                float ms = 0;
-                PT_HIP(hipEventElapsedTime(&ms, e0, e1));
-                ms_best_trial = std::min(ms_best_trial, ms);
-            }
-            if (ms_best_trial < best_ms) {
-                best_ms = ms_best_trial;
-                best_b = bs;
-                best_i = ni;
-            }
+    for (int bs : {256, 512, 1024}) {
+        if (configure_shape(plan, bs) != PT_OK) continue;
+        float trial = 1e30f;
+        for (int rep = 0; rep < 2; ++rep) {
+            PT_HIP(hipMemcpyAsync(plan->d_scratch, d_brlen, nb, hipMemcpyDeviceToDevice, s));
+            PT_HIP(hipEventRecord(e0, s));
+            st = enqueue(plan, PT_PLAN_OPTIMIZE, nullptr, plan->d_scratch, &p, d_lnl, nullptr, nullptr, nullptr,
+                         nullptr, s);
+            if (st) return st;
+            PT_HIP(hipEventRecord(e1, s));
+            PT_HIP(hipEventSynchronize(e1));
+            float ms = 0;
+            PT_HIP(hipEventElapsedTime(&ms, e0, e1));
+            trial = std::min(trial, ms);
         }
+        if (trial < best_ms) {
+            best_ms = trial;
+            best_b = bs;
+        }
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    plan->opt_block = best_b;
-    plan->opt_items = best_i;
-    plan->opt_grid = 0;
+    if ((st = configure_shape(plan, best_b))) return st;
     for (auto &kv : plan->execs) (void)hipGraphExecDestroy(kv.second);
     plan->execs.clear();
-    plan->ctx->tuned[std::make_tuple(plan->precision, plan->kp, plan->max_items)] = {best_b, best_i};
-    if (block) *block = best_b;
-    if (items) *items = best_i;
+    plan->ctx->tuned[std::make_tuple(plan->precision, plan->kp, plan->max_P)] = best_b;
+    if (block) *block = plan->opt_block;
+    if (items) *items = plan->opt_items;
+    return PT_OK;
+}
+
+pt_status pt_plan_traffic(const pt_plan *plan, int32_t kind, const int32_t *passes, double *bytes_out) {
+    if (!plan || !bytes_out) return fail(PT_EINVAL, "NULL argument");
+    if (!(plan->kinds & kind) || (kind != PT_PLAN_LOGLIK && kind != PT_PLAN_GRAD && kind != PT_PLAN_OPTIMIZE))
+        return fail(PT_EINVAL, "kind not in this plan");
+    const std::vector<TreeDev> &tv = kind == PT_PLAN_LOGLIK ? plan->tll_h : kind == PT_PLAN_GRAD ? plan->tgr_h : plan->top_h;
+    const double b = (double)store_bytes(plan->precision);
+    double total = 0.0;
+    for (int t = 0; t < plan->n_trees; ++t) {
+        const AlnDev &a = plan->alns_h[tv[t].aln];
+        const double slot = (double)a.P * a.K * 4 * b + (double)a.P * 2, tip = (double)a.P;
+        auto side = [&](int ref) { return ref < 0 ? tip : slot; };
+        auto prog = [&](int o0, int no) {
+            double s2 = 0.0;
+            for (int o = 0; o < no; ++o) {
+                const Op &op = plan->ops_h[o0 + o];
+                if (op.code == pt::OP_UPDATE) s2 += side(op.a) + side(op.b) + slot;
+                else s2 += side(op.a) + side(op.b) + 8.0 * a.P;
+            }
+            return s2;
+        };
+        double bt = prog(tv[t].op_first, tv[t].n_first);
+        if (kind == PT_PLAN_OPTIMIZE) {
+            int ps = passes ? passes[t] : 1;
+            if (ps > 1) bt += (ps - 1) * prog(tv[t].op_steady, tv[t].n_steady);
+        }
+        total += bt;
+    }
+    *bytes_out = total;
+    return PT_OK;
+}
+
+pt_status pt_plan_set_profile(pt_plan *plan, void *d_counters) {
+    if (!plan) return fail(PT_EINVAL, "plan is NULL");
+    plan->d_prof = reinterpret_cast<long long *>(d_counters);
+    for (auto &kv : plan->execs) (void)hipGraphExecDestroy(kv.second);
+    plan->execs.clear();
     return PT_OK;
 }
 

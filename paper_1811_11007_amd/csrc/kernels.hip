@@ -1,12 +1,12 @@
 // kernels.hip -- CDNA4 (gfx950) kernels of the tree likelihood.
 //
-// Work decomposition.  An item is one (site pattern, rate category) pair;
-// the Kp items of a pattern occupy adjacent lanes of a 64-wide wavefront.
-// A thread keeps the same category k for all its items, so the 4x4
-// transition matrix it applies is the same for all of them and is read from
-// LDS as a wave-uniform-per-k broadcast.  Partials are stored pattern-major,
-// [slot][item][4], so one wavefront load of its 64 items is one contiguous
-// 1 KiB (FP32) or 2 KiB (FP64) block.
+// Work decomposition.  One thread owns one site pattern at a time and
+// handles all of its rate categories, so the per-pattern scaling decision,
+// the sum over categories and the logarithm stay inside the thread.  Partials
+// are stored category-major per slot, [slot][Kp][P][4], so for a fixed
+// category a wavefront's 64 patterns are one contiguous 1 KiB (FP32) or
+// 2 KiB (FP64) block: every load and store is fully coalesced.  Transition
+// matrices sit in LDS and are read with wave-uniform addresses (broadcast).
 //
 // Numerics.  Partials may be stored in FP32; every product, transition
 // matrix, logarithm and sum over patterns is FP64.  Per-pattern scaling
@@ -21,6 +21,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <type_traits>
 
 #include "kernels.hpp"
 #include "pt.h"
@@ -60,22 +61,24 @@ struct Store<double> {
     }
 };
 
-// Model constants of the tree in flight, copied to LDS once per tree so the
-// inner loops read them as broadcasts instead of holding them in registers.
+// Model constants of the tree in flight, copied to LDS once per tree.
 struct ModelS {
-    double pU[16];   // pi_i U_im
-    double Ui[16];   // Uinv_mj
+    double W[16];    // W_im = pi_i U_im = Uinv_mi
     double lam[4];
     double rate[kMaxCats];
 };
 
 __device__ inline void model_to_lds(const AlnDev *aln, ModelS *m) {
-    for (int x = threadIdx.x; x < 16; x += blockDim.x) {
-        m->pU[x] = aln->freqs[x >> 2] * aln->U[x];
-        m->Ui[x] = aln->Uinv[x];
-    }
+    for (int x = threadIdx.x; x < 16; x += blockDim.x) m->W[x] = aln->W[x];
     if (threadIdx.x < 4) m->lam[threadIdx.x] = aln->lam[threadIdx.x];
     if (threadIdx.x < kMaxCats) m->rate[threadIdx.x] = aln->rate[threadIdx.x];
+}
+
+// Load through a pointer known to address global memory (pointers read out
+// of descriptors would otherwise be accessed with generic FLAT loads).
+template <typename X>
+__device__ inline X ldg(const X *p) {
+    return *(const __attribute__((address_space(1))) X *)p;
 }
 
 // View of one tree's data for the device functions below.
@@ -85,31 +88,36 @@ struct TreeView {
     const double *pm;    // LDS: [E][Kp][16]
     const uint8_t *tips; // [n][P]
     const double *w;     // [P]
-    T *clv;              // slot 0 of this tree
-    uint16_t *cnt;       // slot 0 of this tree
-    int P, K, Kp, kshift, items;
+    T *clv;              // slot 0 of this tree: [slot][Kp][P][4]
+    uint16_t *cnt;       // slot 0 of this tree: [slot][P]
+    int P, K;
 };
 
-template <typename T>
-__device__ inline void load_side(const TreeView<T> &v, int ref, int it, int p, double x[4], int &c) {
-    if (ref < 0) {
-        unsigned code = v.tips[(size_t)(-ref - 1) * v.P + p];
-        x[0] = code & 1u; x[1] = (code >> 1) & 1u; x[2] = (code >> 2) & 1u; x[3] = (code >> 3) & 1u;
-        c = 0;
-    } else {
-        Store<T>::load(v.clv + ((size_t)ref * v.items + it) * 4, x);
-        c = v.cnt[(size_t)ref * v.P + p];
-    }
+template <typename T, int KP>
+__device__ inline T *slot_ptr(const TreeView<T> &v, int ref, int k, int p) {
+    return v.clv + (((size_t)ref * KP + k) * v.P + p) * 4;
 }
 
-__device__ inline double group_max(double x, int Kp) {
-    for (int m = 1; m < Kp; m <<= 1) x = fmax(x, __shfl_xor(x, m, 64));
-    return x;
+__device__ inline void tip_vec(unsigned code, double x[4]) {
+    x[0] = code & 1u; x[1] = (code >> 1) & 1u; x[2] = (code >> 2) & 1u; x[3] = (code >> 3) & 1u;
 }
 
-__device__ inline double group_sum(double x, int Kp) {
-    for (int m = 1; m < Kp; m <<= 1) x += __shfl_xor(x, m, 64);
-    return x;
+// Entry (i, j) of P(r_k t) = U diag(exp(lam r_k t)) Uinv.
+__device__ inline double pm_entry(const AlnDev *aln, int k, int ij, double t) {
+    const int i = ij >> 2, j = ij & 3;
+    const double r = aln->rate[k];
+    double s = 0.0;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) s += aln->U[i * 4 + m] * exp(aln->lam[m] * r * t) * aln->Uinv[m * 4 + j];
+    return s;
+}
+
+// 1 / x from the hardware estimate plus two Newton-Raphson steps.
+__device__ inline double recip(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return r;
 }
 
 // Fixed-order block sum of three values; every thread receives the totals.
@@ -141,149 +149,125 @@ __device__ inline void block_sum3(double &a, double &b, double &c, double *red, 
     parity ^= 1;
 }
 
-// Entry (i, j) of P(r_k t) = U diag(exp(lam r_k t)) Uinv.
-__device__ inline double pm_entry(const AlnDev *aln, int k, int ij, double t) {
-    const int i = ij >> 2, j = ij & 3;
-    const double r = aln->rate[k];
-    double s = 0.0;
-#pragma unroll
-    for (int m = 0; m < 4; ++m) s += aln->U[i * 4 + m] * exp(aln->lam[m] * r * t) * aln->Uinv[m * 4 + j];
-    return s;
+// Per-wave table of exp(lam_m r_k t) and its first two t-derivative factors:
+// wx[km] = e, wx[32 + km] = lam_m r_k e, wx[64 + km] = (lam_m r_k)^2 e, with
+// km = k*4 + m.  Lanes 0..4K-1 compute one entry each; LDS operations of a
+// wave complete in order, so the wave's later reads see them.
+constexpr int kWx = 3 * 4 * kMaxCats;  // doubles per wave
+
+__device__ inline void wave_expo(double *wx, const ModelS *md, int K, double t) {
+    const int lane = threadIdx.x & 63;
+    if (lane < 4 * K) {
+        const int k = lane >> 2, m = lane & 3;
+        const double q = md->lam[m] * md->rate[k];
+        const double e = exp(q * t);
+        wx[lane] = e;
+        wx[4 * kMaxCats + lane] = e * q;
+        wx[8 * kMaxCats + lane] = e * q * q;
+    }
+    __builtin_amdgcn_wave_barrier();
 }
 
-// OP_UPDATE over this thread's items:
-//   dst = (P(t_ea) . side a) * (P(t_eb) . side b), elementwise over states,
-// with per-pattern scaling.
-// Returns p unchanged but opaque to the optimiser, so loads through it stay
-// inside the op that needs them instead of being hoisted out of the op loop
-// and pinned in registers for the whole kernel.
-template <typename P>
-__device__ inline P *opaque(P *p) {
-    __asm__ volatile("" : "+s"(p));
-    return p;
-}
-
-template <typename T, int BS, int NI>
-__device__ inline void do_update(const TreeView<T> v, const Op op, int base) {
-    const int tid = threadIdx.x;
-    const int k = tid & (v.Kp - 1);
-    const bool kval = k < v.K;
-    const double *pm = opaque(v.pm);
-    const double *Pa = pm + ((size_t)op.ea * v.Kp + k) * 16;
-    const double *Pb = pm + ((size_t)op.eb * v.Kp + k) * 16;
+// OP_UPDATE for this thread's patterns:
+//   dst[k] = (P_k(t_ea) . side a[k]) * (P_k(t_eb) . side b[k]), elementwise over
+// states, for every category k, then per-pattern scaling.
+template <typename T, int BS, int KP>
+__device__ inline void do_update(const TreeView<T> &v, const Op &op, int base, int ni) {
+    const double *pm = v.pm;
     const double thr = ldexp(1.0, -Store<T>::kScaleExp);
     const double up = ldexp(1.0, Store<T>::kScaleExp);
 #pragma unroll 1
-    for (int j = 0; j < NI; ++j) {
-        const int it = base + j * BS + tid;
-        const bool valid = it < v.items;
-        const int p = it >> v.kshift;
-        double xa[4] = {0, 0, 0, 0}, xb[4] = {0, 0, 0, 0};
-        int ca = 0, cb = 0;
-        if (valid) {
-            load_side(v, op.a, it, p, xa, ca);
-            load_side(v, op.b, it, p, xb, cb);
-        }
-        double o[4], mx = 0.0;
+    for (int j = 0; j < ni; ++j) {
+        const int p = base + j * BS + threadIdx.x;
+        if (p >= v.P) break;
+        int c = 0;
+        unsigned ta = 0, tb = 0;
+        if (op.a < 0) ta = ldg(v.tips + (size_t)(-op.a - 1) * v.P + p);
+        else c += v.cnt[(size_t)op.a * v.P + p];
+        if (op.b < 0) tb = ldg(v.tips + (size_t)(-op.b - 1) * v.P + p);
+        else c += v.cnt[(size_t)op.b * v.P + p];
+        // All categories' loads are issued before any arithmetic; the layout
+        // holds KP categories, so padded ones are in bounds and ignored.
+        double xa[KP][4], xb[KP][4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            double sa = Pa[i * 4 + 0] * xa[0] + Pa[i * 4 + 1] * xa[1] + Pa[i * 4 + 2] * xa[2] + Pa[i * 4 + 3] * xa[3];
-            double sb = Pb[i * 4 + 0] * xb[0] + Pb[i * 4 + 1] * xb[1] + Pb[i * 4 + 2] * xb[2] + Pb[i * 4 + 3] * xb[3];
-            o[i] = kval ? sa * sb : 0.0;
-            mx = fmax(mx, o[i]);
+        for (int k = 0; k < KP; ++k) {
+            if (op.a < 0) tip_vec(ta, xa[k]);
+            else Store<T>::load(slot_ptr<T, KP>(v, op.a, k, p), xa[k]);
+            if (op.b < 0) tip_vec(tb, xb[k]);
+            else Store<T>::load(slot_ptr<T, KP>(v, op.b, k, p), xb[k]);
         }
-        mx = group_max(mx, v.Kp);
-        int c = ca + cb;
-        if (mx < thr && mx > 0.0) {
+        double o[KP][4];
+        double mx = 0.0;
 #pragma unroll
-            for (int i = 0; i < 4; ++i) o[i] *= up;
-            c += 1;
-        }
-        if (valid) {
-            Store<T>::store(v.clv + ((size_t)op.dst * v.items + it) * 4, o);
-            v.cnt[(size_t)op.dst * v.P + p] = (uint16_t)c;  // every lane of the pattern writes the same value
-        }
-    }
-}
-
-// Per-edge eigenbasis table ("sumtable") of this thread's items across an
-// edge with sides a and b:  s_m = (sum_i pi_i A_i U_im) (sum_j Uinv_mj B_j),
-// so that L(t) = sum_m s_m exp(lam_m r_k t) for the item's category.
-// wl = pattern weight on the first lane of a valid pattern, else 0;
-// returns this thread's share of the t-independent part of lnL (scaler
-// corrections and the 1/K category weight).
-template <typename T, typename S, int BS, int NI>
-__device__ inline double build_sumtable(const TreeView<T> &v, int a, int b, int base,
-                                        S s[NI][4], double wl[NI]) {
-    const ModelS *md = opaque(v.m);
-    const int tid = threadIdx.x;
-    const int k = tid & (v.Kp - 1);
-    const double logK = log((double)v.K);
-    double cterm = 0.0;
-#pragma unroll
-    for (int j = 0; j < NI; ++j) {
-        const int it = base + j * BS + tid;
-        const bool valid = it < v.items;
-        const int p = it >> v.kshift;
-        double xa[4] = {0, 0, 0, 0}, xb[4] = {0, 0, 0, 0};
-        int ca = 0, cb = 0;
-        if (valid) {
-            load_side(v, a, it, p, xa, ca);
-            load_side(v, b, it, p, xb, cb);
-        }
-        const bool live = valid && k < v.K;
-#pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            double ua = 0.0, vb = 0.0;
+        for (int k = 0; k < KP; ++k) {
+            const double *Pa = pm + ((size_t)op.ea * KP + k) * 16;
+            const double *Pb = pm + ((size_t)op.eb * KP + k) * 16;
+            const bool live = k < v.K;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                ua += md->pU[i * 4 + m] * xa[i];
-                vb += md->Ui[m * 4 + i] * xb[i];
+                const double sa = Pa[i * 4] * xa[k][0] + Pa[i * 4 + 1] * xa[k][1] + Pa[i * 4 + 2] * xa[k][2] +
+                                  Pa[i * 4 + 3] * xa[k][3];
+                const double sb = Pb[i * 4] * xb[k][0] + Pb[i * 4 + 1] * xb[k][1] + Pb[i * 4 + 2] * xb[k][2] +
+                                  Pb[i * 4 + 3] * xb[k][3];
+                o[k][i] = live ? sa * sb : 0.0;
+                mx = fmax(mx, o[k][i]);
             }
-            s[j][m] = live ? (S)(ua * vb) : (S)0;
         }
-        const bool lead = valid && k == 0;
-        const double w = lead ? v.w[p] : 0.0;
-        wl[j] = w;
-        cterm -= w * ((double)(ca + cb) * Store<T>::kScaleExp * kLn2 + logK);
+        if (mx < thr && mx > 0.0) {
+#pragma unroll
+            for (int k = 0; k < KP; ++k)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) o[k][i] *= up;
+            c += 1;
+        }
+#pragma unroll
+        for (int k = 0; k < KP; ++k)
+            if (k < v.K) Store<T>::store(slot_ptr<T, KP>(v, op.dst, k, p), o[k]);
+        v.cnt[(size_t)op.dst * v.P + p] = (uint16_t)c;
     }
-    return cterm;
 }
 
-// This thread's shares of lnL, d lnL/dt, d2 lnL/dt2 at length t.
-template <typename S, int BS, int NI>
-__device__ inline void eval_sumtable(const ModelS *md_in, int Kp, double t, const S s[NI][4],
-                                     const double wl[NI], double &l0, double &l1, double &l2) {
-    const ModelS *md = opaque(md_in);
-    const int k = threadIdx.x & (Kp - 1);
-    const double r = md->rate[k];
-    double e[4], q1[4], q2[4];
+// Eigenbasis coefficients of pattern p, category k, across an edge with
+// sides a and b:  s_m = (sum_i pi_i A_i U_im)(sum_j Uinv_mj B_j)
+// = (sum_i W_im A_i)(sum_j W_jm B_j), so L_k(t) = sum_m s_m exp(lam_m r_k t).
+template <typename T, int KP>
+__device__ inline void coeffs(const TreeView<T> &v, const ModelS *md, int a, int b, unsigned ta, unsigned tb,
+                              int k, int p, double s[4]) {
+    double xa[4], xb[4];
+    if (a < 0) tip_vec(ta, xa);
+    else Store<T>::load(slot_ptr<T, KP>(v, a, k, p), xa);
+    if (b < 0) tip_vec(tb, xb);
+    else Store<T>::load(slot_ptr<T, KP>(v, b, k, p), xb);
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
-        q1[m] = md->lam[m] * r;
-        q2[m] = q1[m] * q1[m];
-        e[m] = exp(q1[m] * t);
-    }
+        double ua = 0.0, vb = 0.0;
 #pragma unroll
-    for (int j = 0; j < NI; ++j) {
-        double L = 0.0, L1 = 0.0, L2 = 0.0;
-#pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            const double se = (double)s[j][m] * e[m];
-            L += se;
-            L1 += se * q1[m];
-            L2 += se * q2[m];
+        for (int i = 0; i < 4; ++i) {
+            const double wim = md->W[i * 4 + m];
+            ua += wim * xa[i];
+            vb += wim * xb[i];
         }
-        L = group_sum(L, Kp);
-        L1 = group_sum(L1, Kp);
-        L2 = group_sum(L2, Kp);
-        if (wl[j] != 0.0) {
-            const double r1 = L1 / L;
-            l0 += wl[j] * log(L);
-            l1 += wl[j] * r1;
-            l2 += wl[j] * (L2 / L - r1 * r1);
-        }
+        s[m] = ua * vb;
     }
+}
+
+// Tip codes of the two sides (0 for partials) and the pattern's scaler total.
+template <typename T>
+__device__ inline int side_codes(const TreeView<T> &v, int a, int b, int p, unsigned &ta, unsigned &tb) {
+    int c = 0;
+    ta = tb = 0;
+    if (a < 0) ta = ldg(v.tips + (size_t)(-a - 1) * v.P + p);
+    else c += v.cnt[(size_t)a * v.P + p];
+    if (b < 0) tb = ldg(v.tips + (size_t)(-b - 1) * v.P + p);
+    else c += v.cnt[(size_t)b * v.P + p];
+    return c;
+}
+
+// t-independent part of a pattern's lnL: scaler corrections and the 1/K
+// category weight.
+template <typename T>
+__device__ inline double const_term(int c, double logK) {
+    return -((double)c * Store<T>::kScaleExp * kLn2 + logK);
 }
 
 struct Sums3 {
@@ -291,17 +275,44 @@ struct Sums3 {
     int parity;
 };
 
-// OP_EVAL: block totals of lnL and its first two derivatives across edge
-// e at length t.
-template <typename T, int BS, int NI>
-__device__ inline Sums3 eval_edge(const TreeView<T> v, int a, int b, int base, double t, double *red,
-                                        int parity) {
-    T s[NI][4];
-    double wl[NI];
+// OP_EVAL: block totals of lnL and its first two derivatives across an edge
+// at length t, computed on the fly from the two sides.
+template <typename T, int BS, int KP>
+__device__ inline Sums3 eval_edge(const TreeView<T> &v, int a, int b, int base, int ni, double t, double *red,
+                                  double *wx, int parity) {
+    const ModelS *md = v.m;
+    wave_expo(wx, md, v.K, t);
+    const double logK = log((double)v.K);
     Sums3 r;
-    r.l0 = build_sumtable<T, T, BS, NI>(v, a, b, base, s, wl);
-    r.l1 = r.l2 = 0.0;
-    eval_sumtable<T, BS, NI>(v.m, v.Kp, t, s, wl, r.l0, r.l1, r.l2);
+    r.l0 = r.l1 = r.l2 = 0.0;
+#pragma unroll 1
+    for (int j = 0; j < ni; ++j) {
+        const int p = base + j * BS + threadIdx.x;
+        if (p >= v.P) break;
+        unsigned ta, tb;
+        const int c = side_codes(v, a, b, p, ta, tb);
+        double s[KP][4];
+#pragma unroll
+        for (int k = 0; k < KP; ++k) coeffs<T, KP>(v, md, a, b, ta, tb, k, p, s[k]);
+        double L = 0.0, L1 = 0.0, L2 = 0.0;
+#pragma unroll
+        for (int k = 0; k < KP; ++k) {
+            if (k < v.K) {
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    L += s[k][m] * wx[k * 4 + m];
+                    L1 += s[k][m] * wx[4 * kMaxCats + k * 4 + m];
+                    L2 += s[k][m] * wx[8 * kMaxCats + k * 4 + m];
+                }
+            }
+        }
+        const double w = ldg(v.w + p);
+        const double inv = recip(L);
+        const double r1 = L1 * inv;
+        r.l0 += w * (log(L) + const_term<T>(c, logK));
+        r.l1 += w * r1;
+        r.l2 += w * (L2 * inv - r1 * r1);
+    }
     block_sum3<BS>(r.l0, r.l1, r.l2, red, parity);
     r.parity = parity;
     return r;
@@ -309,33 +320,83 @@ __device__ inline Sums3 eval_edge(const TreeView<T> v, int a, int b, int base, d
 
 struct EdgeResult {
     double t, lnl;
-    int parity;
+    int parity, iters;
+    long long cyc_table, cyc_iters;
 };
 
 // OP_NEWTON: safeguarded, projected Newton on the length of one edge.
+//  - the eigenbasis coefficients of this thread's patterns are computed once
+//    into `tab` (layout [k][row][4], rows = BS*ni pattern slots) and the
+//    pattern weights into `wrow` (in LDS, or in a per-block global buffer),
+//    then every iteration is a pass over them plus one block sum;
 //  - the bracket (lo, hi) starts as [t_min, t_max] and shrinks to t on the
 //    side the first derivative points away from;
 //  - a Newton step is taken when d2 < 0 and it stays in the bracket (the
 //    original bounds count as inside), else the bracket is bisected
 //    geometrically;
 //  - a bound with the derivative pointing outwards is an optimum;
-//  - a step of at most tol * max(t, 1e-6) is converged and not taken, so
-//    the returned lnL is the one evaluated at the returned t.
+//  - a step of at most tol * max(t, 1e-6) is converged and not taken;
+//  - with want_lnl, lnL is evaluated at the returned t.
 // All threads hold identical block totals, so every thread takes the same
 // decisions.
-template <typename T, int BS, int NI>
-__device__ inline EdgeResult newton_edge(const TreeView<T> v, int a, int b, double t, const OptParams opt,
-                                               double *red, int parity) {
-    T s[NI][4];
-    double wl[NI];
-    const double cterm = build_sumtable<T, T, BS, NI>(v, a, b, 0, s, wl);
-    double lo = opt.t_min, hi = opt.t_max, lnl = 0.0;
-    for (int it = 1;; ++it) {
-        double l0 = cterm, d1 = 0.0, d2 = 0.0;
-        eval_sumtable<T, BS, NI>(v.m, v.Kp, t, s, wl, l0, d1, d2);
-        block_sum3<BS>(l0, d1, d2, red, parity);
-        lnl = l0;
-        if (it >= opt.max_newton) break;
+template <typename T, int BS, int KP>
+__device__ inline EdgeResult newton_edge(const TreeView<T> &v, int a, int b, double t, bool want_lnl,
+                                         const OptParams &opt, T *tab, double *wrow, int ni, double *red,
+                                         double *wx, int parity) {
+    const ModelS *md = v.m;
+    const size_t rows = (size_t)BS * ni;
+    const double logK = log((double)v.K);
+    const long long c0 = clock64();
+    double cterm = 0.0;
+#pragma unroll 1
+    for (int j = 0; j < ni; ++j) {
+        const int p = j * BS + threadIdx.x;
+        if (p >= v.P) break;
+        unsigned ta, tb;
+        const int c = side_codes(v, a, b, p, ta, tb);
+        const double w = ldg(v.w + p);
+        cterm += w * const_term<T>(c, logK);
+        wrow[j * BS + threadIdx.x] = w;
+        double s[KP][4];
+#pragma unroll
+        for (int k = 0; k < KP; ++k) coeffs<T, KP>(v, md, a, b, ta, tb, k, p, s[k]);
+#pragma unroll
+        for (int k = 0; k < KP; ++k)
+            if (k < v.K) Store<T>::store(tab + ((size_t)k * rows + j * BS + threadIdx.x) * 4, s[k]);
+    }
+    const long long c1 = clock64();
+    double lo = opt.t_min, hi = opt.t_max;
+    int iter = 1;
+    for (;; ++iter) {
+        wave_expo(wx, v.m, v.K, t);
+        double d0 = 0.0, d1 = 0.0, d2 = 0.0;
+#pragma unroll 1
+        for (int j = 0; j < ni; ++j) {
+            const int p = j * BS + threadIdx.x;
+            if (p >= v.P) break;
+            double s[KP][4];
+#pragma unroll
+            for (int k = 0; k < KP; ++k) Store<T>::load(tab + ((size_t)k * rows + j * BS + threadIdx.x) * 4, s[k]);
+            const double w = wrow[j * BS + threadIdx.x];
+            double L = 0.0, L1 = 0.0, L2 = 0.0;
+#pragma unroll
+            for (int k = 0; k < KP; ++k) {
+                if (k < v.K) {
+#pragma unroll
+                    for (int m = 0; m < 4; ++m) {
+                        L += s[k][m] * wx[k * 4 + m];
+                        L1 += s[k][m] * wx[4 * kMaxCats + k * 4 + m];
+                        L2 += s[k][m] * wx[8 * kMaxCats + k * 4 + m];
+                    }
+                }
+            }
+            const double inv = recip(L);
+            const double r1 = L1 * inv;
+            d1 += w * r1;
+            d2 += w * (L2 * inv - r1 * r1);
+        }
+        block_sum3<BS>(d0, d1, d2, red, parity);
+        if (iter >= opt.max_newton) break;
         if (d1 > 0.0) lo = t;
         else if (d1 < 0.0) hi = t;
         else break;
@@ -349,10 +410,35 @@ __device__ inline EdgeResult newton_edge(const TreeView<T> v, int a, int b, doub
         if (fabs(tn - t) <= opt.tol_newton * fmax(t, 1e-6)) break;
         t = tn;
     }
+    double lnl = 0.0;
+    if (want_lnl) {
+        wave_expo(wx, v.m, v.K, t);
+        double l0 = cterm, z1 = 0.0, z2 = 0.0;
+#pragma unroll 1
+        for (int j = 0; j < ni; ++j) {
+            const int p = j * BS + threadIdx.x;
+            if (p >= v.P) break;
+            double s[KP][4];
+#pragma unroll
+            for (int k = 0; k < KP; ++k) Store<T>::load(tab + ((size_t)k * rows + j * BS + threadIdx.x) * 4, s[k]);
+            double L = 0.0;
+#pragma unroll
+            for (int k = 0; k < KP; ++k)
+                if (k < v.K)
+#pragma unroll
+                    for (int m = 0; m < 4; ++m) L += s[k][m] * wx[k * 4 + m];
+            l0 += wrow[j * BS + threadIdx.x] * log(L);
+        }
+        block_sum3<BS>(l0, z1, z2, red, parity);
+        lnl = l0;
+    }
     EdgeResult r;
     r.t = t;
     r.lnl = lnl;
     r.parity = parity;
+    r.iters = iter;
+    r.cyc_table = c1 - c0;
+    r.cyc_iters = clock64() - c1;
     return r;
 }
 
@@ -368,9 +454,6 @@ __device__ inline TreeView<T> make_view(const TreeDev &td, const AlnDev *aln, co
     v.cnt = a.cnt + td.cnt_off;
     v.P = aln->P;
     v.K = aln->K;
-    v.Kp = aln->Kp;
-    v.kshift = __ffs(aln->Kp) - 1;
-    v.items = aln->P * aln->Kp;
     return v;
 }
 
@@ -387,7 +470,7 @@ __global__ void k_pmat(const BatchArgs a, const double *brlen) {
     if (fe >= a.n_edges) return;
     const TreeDev &td = a.trees[a.edge_tree[fe]];
     const AlnDev *aln = a.alns + td.aln;
-    const int Kp = aln->Kp;
+    const int Kp = a.kp;
     const double t = brlen[fe];
     double *out = a.pmat + td.pm_off + (fe - td.edge_off) * Kp * 16;
     for (int k = 0; k < Kp; ++k) {
@@ -403,30 +486,33 @@ __global__ void k_pmat(const BatchArgs a, const double *brlen) {
 }
 
 // Pattern-tile kernel: each block runs its tree's program over one tile of
-// items.  LOGLIK programs end in one EVAL (column 0); GRAD programs EVAL
-// every edge.  Output: part[tile][col] = (lnL, d1, d2) partial sums.
-template <typename T, int BS, int NI>
+// BS * kTileItems patterns.  LOGLIK programs end in one EVAL (column 0);
+// GRAD programs EVAL every edge.  Output: part[tile][col] = (lnL, d1, d2).
+template <typename T, int BS, int KP>
 __global__ void __launch_bounds__(BS) k_tiles(const BatchArgs a, const double *brlen) {
     extern __shared__ double lds[];
     __shared__ double red[2 * (BS / 64) * 3];
+    __shared__ double wxs[(BS / 64) * kWx];
     __shared__ ModelS model;
     const int tile = blockIdx.x;
     const TreeDev td = a.trees[a.tile_tree[tile]];
     const AlnDev *aln = a.alns + td.aln;
-    const int n_pm = td.n_edges * aln->Kp * 16;
+    const int n_pm = td.n_edges * KP * 16;
     for (int i = threadIdx.x; i < n_pm; i += BS) lds[i] = a.pmat[td.pm_off + i];
     model_to_lds(aln, &model);
     __syncthreads();
     const TreeView<T> v = make_view<T>(td, aln, a, &model, lds);
-    const int base = (tile - td.tile_begin) * BS * NI;
+    double *wx = wxs + (threadIdx.x >> 6) * kWx;
+    const int base = (tile - td.tile_begin) * BS * kTileItems;
     int parity = 0;
     for (int o = 0; o < td.n_first; ++o) {
         const Op op = a.ops[td.op_first + o];
         if (op.code == OP_UPDATE) {
-            do_update<T, BS, NI>(v, op, base);
+            do_update<T, BS, KP>(v, op, base, kTileItems);
             continue;
         }
-        const Sums3 r = eval_edge<T, BS, NI>(v, op.a, op.b, base, brlen[td.edge_off + op.dst], red, parity);
+        const Sums3 r =
+            eval_edge<T, BS, KP>(v, op.a, op.b, base, kTileItems, brlen[td.edge_off + op.dst], red, wx, parity);
         parity = r.parity;
         if (threadIdx.x == 0) {
             double *out = a.part + ((size_t)tile * a.part_cols + op.ea) * 3;
@@ -470,15 +556,26 @@ __global__ void k_reduce(const BatchArgs a, bool grad, double *lnl, double *gout
 // whole smoothing loop -- partial updates, per-edge Newton iterations with
 // block reductions, pass-level convergence -- without leaving the kernel.
 // Every wave exits once the counter passes the number of trees.
-template <typename T, int BS, int NI>
-__global__ void __launch_bounds__(BS) k_optimize(const BatchArgs a, double *brlen, const OptParams opt,
-                                                 double *lnl_out, int32_t *passes_out,
+// Each thread owns patterns tid + j*BS, j < ni (ni*BS >= patterns of every
+// tree).  TAB_LDS: the per-edge eigenbasis table lives in LDS after the
+// transition matrices; otherwise in a per-block slice of a.tab.
+template <typename T, int BS, int KP, bool TAB_LDS>
+__global__ void __launch_bounds__(BS) k_optimize(const BatchArgs a, double *brlen, const OptParams opt, int ni,
+                                                 int pm_lds_doubles, double *lnl_out, int32_t *passes_out,
                                                  int32_t *status_out) {
     extern __shared__ double lds[];
     __shared__ double red[2 * (BS / 64) * 3];
+    __shared__ double wxs[(BS / 64) * kWx];
     __shared__ ModelS model;
     __shared__ int q_sh;
     const int tid = threadIdx.x;
+    double *wx = wxs + (tid >> 6) * kWx;
+    // per block: the table [KP][BS*ni][4] of T, then the weights [BS*ni]
+    const size_t tab_bytes = (size_t)BS * ni * KP * 4 * sizeof(T);
+    char *tab_base = TAB_LDS ? reinterpret_cast<char *>(lds + pm_lds_doubles)
+                             : reinterpret_cast<char *>(a.tab) + (size_t)blockIdx.x * (tab_bytes + (size_t)BS * ni * 8);
+    T *tab = reinterpret_cast<T *>(tab_base);
+    double *wrow = reinterpret_cast<double *>(tab_base + tab_bytes);
     for (;;) {
         if (tid == 0) q_sh = atomicAdd(a.queue, 1);
         __syncthreads();
@@ -487,14 +584,14 @@ __global__ void __launch_bounds__(BS) k_optimize(const BatchArgs a, double *brle
         const int b = a.order[q];
         const TreeDev td = a.trees[b];
         const AlnDev *aln = a.alns + td.aln;
-        const int E = td.n_edges, Kp = aln->Kp;
+        const int E = td.n_edges;
         double *pm = lds;
-        double *tl = lds + (size_t)E * Kp * 16;
+        double *tl = lds + (size_t)E * KP * 16;
         for (int e = tid; e < E; e += BS) tl[e] = fmin(fmax(brlen[td.edge_off + e], opt.t_min), opt.t_max);
         model_to_lds(aln, &model);
         __syncthreads();
-        for (int x = tid; x < E * Kp * 16; x += BS) {
-            const int e = x / (Kp * 16), r = x % (Kp * 16);
+        for (int x = tid; x < E * KP * 16; x += BS) {
+            const int e = x / (KP * 16), r = x % (KP * 16);
             pm[x] = pm_entry(aln, r >> 4, r & 15, tl[e]);
         }
         __syncthreads();
@@ -503,6 +600,8 @@ __global__ void __launch_bounds__(BS) k_optimize(const BatchArgs a, double *brle
         double prev = -INFINITY, cur = -INFINITY;
         int passes = 0;
         bool converged = false;
+        long long pc[PROF_FIELDS] = {0, 0, 0, 0, 0, 0, 0, 0};
+        const long long t_start = clock64();
         for (;;) {
             const bool first = passes == 0;
             const int o0 = first ? td.op_first : td.op_steady;
@@ -511,24 +610,35 @@ __global__ void __launch_bounds__(BS) k_optimize(const BatchArgs a, double *brle
             for (int o = 0; o < no; ++o) {
                 const Op op = a.ops[o0 + o];
                 if (op.code == OP_UPDATE) {
-                    do_update<T, BS, NI>(v, op, 0);
+                    const long long u0 = a.prof ? clock64() : 0;
+                    do_update<T, BS, KP>(v, op, 0, ni);
+                    if (a.prof) {
+                        pc[PROF_UPDATES] += 1;
+                        pc[PROF_CYC_UPDATE] += clock64() - u0;
+                    }
                     continue;
                 }
                 const int e = op.dst;
                 const double t0 = tl[e];
                 if (op.code == OP_EVAL) {
-                    const Sums3 r = eval_edge<T, BS, NI>(v, op.a, op.b, 0, t0, red, parity);
+                    const Sums3 r = eval_edge<T, BS, KP>(v, op.a, op.b, 0, ni, t0, red, wx, parity);
                     parity = r.parity;
                     cur = r.l0;
                     continue;
                 }
-                const EdgeResult r = newton_edge<T, BS, NI>(v, op.a, op.b, t0, opt, red, parity);
+                // the pass's lnL comes from its last edge step (op.ea = 1)
+                const EdgeResult r =
+                    newton_edge<T, BS, KP>(v, op.a, op.b, t0, op.ea != 0, opt, tab, wrow, ni, red, wx, parity);
                 parity = r.parity;
-                cur = r.lnl;
+                if (op.ea) cur = r.lnl;
+                pc[PROF_EDGE_STEPS] += 1;
+                pc[PROF_NEWTON_ITERS] += r.iters;
+                pc[PROF_CYC_TABLE] += r.cyc_table;
+                pc[PROF_CYC_ITERS] += r.cyc_iters;
                 max_rel = fmax(max_rel, fabs(r.t - t0) / fmax(t0, 1e-6));
                 if (r.t != t0) {
                     if (tid == 0) tl[e] = r.t;
-                    if (tid < Kp * 16) pm[(size_t)e * Kp * 16 + tid] = pm_entry(aln, tid >> 4, tid & 15, r.t);
+                    if (tid < KP * 16) pm[(size_t)e * KP * 16 + tid] = pm_entry(aln, tid >> 4, tid & 15, r.t);
                     __syncthreads();
                 }
             }
@@ -540,7 +650,36 @@ __global__ void __launch_bounds__(BS) k_optimize(const BatchArgs a, double *brle
             if (passes >= opt.max_passes) break;
             prev = cur;
         }
+        if (std::is_same<T, float>::value && td.n_final > 0) {
+            // Report lnL from FP64 partials at the final lengths: one post-order
+            // pass over the same buffer (dense slots; the FP32 partials are no
+            // longer needed, and each thread touches only its own patterns).
+            TreeView<double> vd;
+            vd.m = v.m;
+            vd.pm = v.pm;
+            vd.tips = v.tips;
+            vd.w = v.w;
+            vd.clv = reinterpret_cast<double *>(v.clv);
+            vd.cnt = v.cnt;
+            vd.P = v.P;
+            vd.K = v.K;
+            for (int o = 0; o < td.n_final; ++o) {
+                const Op op = a.ops[td.op_final + o];
+                if (op.code == OP_UPDATE) {
+                    do_update<double, BS, KP>(vd, op, 0, ni);
+                } else {
+                    const Sums3 r = eval_edge<double, BS, KP>(vd, op.a, op.b, 0, ni, tl[op.dst], red, wx, parity);
+                    parity = r.parity;
+                    cur = r.l0;
+                }
+            }
+        }
         for (int e = tid; e < E; e += BS) brlen[td.edge_off + e] = tl[e];
+        if (tid == 0 && a.prof) {
+            pc[PROF_PASSES] = passes;
+            pc[PROF_CYC_TOTAL] = clock64() - t_start;
+            for (int f = 0; f < PROF_FIELDS; ++f) a.prof[(size_t)b * PROF_FIELDS + f] = pc[f];
+        }
         if (tid == 0) {
             lnl_out[b] = cur;
             if (passes_out) passes_out[b] = passes;
@@ -552,54 +691,91 @@ __global__ void __launch_bounds__(BS) k_optimize(const BatchArgs a, double *brle
 
 // ------------------------------------------------------------- dispatch
 
-template <typename T, int BS, int NI>
-hipError_t launch_opt_t(int grid, const BatchArgs &a, double *brlen, const OptParams &opt, double *lnl,
-                        int32_t *passes, int32_t *status, size_t lds, hipStream_t s) {
-    hipLaunchKernelGGL((k_optimize<T, BS, NI>), dim3(grid), dim3(BS), lds, s, a, brlen, opt, lnl, passes,
-                       status);
+template <typename T, int BS, int KP, bool L>
+hipError_t launch_opt_t(int grid, const BatchArgs &a, double *brlen, const OptParams &opt, int ni, int pm_doubles,
+                        double *lnl, int32_t *passes, int32_t *status, size_t lds, hipStream_t s) {
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_optimize<T, BS, KP, L>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL((k_optimize<T, BS, KP, L>), dim3(grid), dim3(BS), lds, s, a, brlen, opt, ni, pm_doubles,
+                       lnl, passes, status);
     return hipGetLastError();
 }
 
-template <typename T, int BS, int NI>
+template <typename T, int BS, int KP, bool L>
 int occ_opt_t(size_t lds) {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_optimize<T, BS, NI>, BS, lds) != hipSuccess) return 0;
+    if (lds > 65536 && hipFuncSetAttribute(reinterpret_cast<const void *>(k_optimize<T, BS, KP, L>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+        return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_optimize<T, BS, KP, L>, BS, lds) != hipSuccess) return 0;
     return n;
 }
 
-#define PT_OPT_SHAPES(X) \
-    X(256, 1) X(256, 2) X(256, 4) X(256, 8) X(256, 12) X(256, 16) \
-    X(512, 1) X(512, 2) X(512, 4) X(512, 8) X(512, 12) X(512, 16) \
-    X(1024, 1) X(1024, 2) X(1024, 4) X(1024, 8) X(1024, 12) X(1024, 16)
+template <typename T, int BS, int KP, bool L>
+size_t spill_opt_t() {
+    hipFuncAttributes at;
+    if (hipFuncGetAttributes(&at, reinterpret_cast<const void *>(k_optimize<T, BS, KP, L>)) != hipSuccess)
+        return ~size_t(0);
+    return at.localSizeBytes;
+}
+
+// Runtime (precision, block, padded categories, table placement) to the
+// matching instantiation of FN.
+#define PT_OPT_CALL(FN, ...)                                                                 \
+    do {                                                                                     \
+        if (block == 256 && precision == PT_FP32)                                            \
+            return tab_lds ? FN<float, 256, KP, true>(__VA_ARGS__) : FN<float, 256, KP, false>(__VA_ARGS__); \
+        if (block == 256)                                                                    \
+            return tab_lds ? FN<double, 256, KP, true>(__VA_ARGS__) : FN<double, 256, KP, false>(__VA_ARGS__); \
+        if (block == 512 && precision == PT_FP32)                                            \
+            return tab_lds ? FN<float, 512, KP, true>(__VA_ARGS__) : FN<float, 512, KP, false>(__VA_ARGS__); \
+        if (block == 512)                                                                    \
+            return tab_lds ? FN<double, 512, KP, true>(__VA_ARGS__) : FN<double, 512, KP, false>(__VA_ARGS__); \
+    } while (0)
+
+#define PT_KP_SWITCH(...)                                   \
+    switch (kp) {                                           \
+    case 1: { constexpr int KP = 1; __VA_ARGS__; } break;   \
+    case 2: { constexpr int KP = 2; __VA_ARGS__; } break;   \
+    case 4: { constexpr int KP = 4; __VA_ARGS__; } break;   \
+    case 8: { constexpr int KP = 8; __VA_ARGS__; } break;   \
+    default: break;                                         \
+    }
+
+template <typename T, int BS, int KP>
+hipError_t launch_tiles_t(const BatchArgs &a, const double *brlen, size_t lds, hipStream_t s) {
+    if (lds > 48 * 1024) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_tiles<T, BS, KP>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL((k_tiles<T, BS, KP>), dim3(a.n_tiles), dim3(BS), lds, s, a, brlen);
+    return hipGetLastError();
+}
 
 }  // namespace
 
 bool optimize_shape_supported(int block, int items) {
-#define X(B, N) if (block == B && items == N) return true;
-    PT_OPT_SHAPES(X)
-#undef X
-    return false;
+    return (block == 256 || block == 512) && items >= 1 && items <= 64;
 }
 
-int optimize_blocks_per_cu(int precision, int block, int items, size_t lds) {
-#define X(B, N)                                                               \
-    if (block == B && items == N)                                             \
-        return precision == PT_FP32 ? occ_opt_t<float, B, N>(lds) : occ_opt_t<double, B, N>(lds);
-    PT_OPT_SHAPES(X)
-#undef X
+int optimize_blocks_per_cu(int precision, int block, int kp, bool tab_lds, size_t lds) {
+    PT_KP_SWITCH(PT_OPT_CALL(occ_opt_t, lds));
     return 0;
 }
 
-hipError_t launch_optimize(int precision, int block, int items, int grid, const BatchArgs &a, double *brlen,
-                           const OptParams &opt, double *lnl, int32_t *passes, int32_t *status, size_t lds,
-                           hipStream_t s) {
-#define X(B, N)                                                                                      \
-    if (block == B && items == N)                                                                    \
-        return precision == PT_FP32                                                                  \
-                   ? launch_opt_t<float, B, N>(grid, a, brlen, opt, lnl, passes, status, lds, s)     \
-                   : launch_opt_t<double, B, N>(grid, a, brlen, opt, lnl, passes, status, lds, s);
-    PT_OPT_SHAPES(X)
-#undef X
+size_t optimize_spill_bytes(int precision, int block, int kp, bool tab_lds) {
+    PT_KP_SWITCH(PT_OPT_CALL(spill_opt_t));
+    return ~size_t(0);
+}
+
+hipError_t launch_optimize(int precision, int block, int kp, int items, bool tab_lds, int pm_doubles, int grid,
+                           const BatchArgs &a, double *brlen, const OptParams &opt, double *lnl, int32_t *passes,
+                           int32_t *status, size_t lds, hipStream_t s) {
+    PT_KP_SWITCH(PT_OPT_CALL(launch_opt_t, grid, a, brlen, opt, items, pm_doubles, lnl, passes, status, lds, s));
     return hipErrorInvalidValue;
 }
 
@@ -615,16 +791,11 @@ hipError_t launch_pmat(const BatchArgs &a, const double *brlen, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_tiles(int precision, bool grad, const BatchArgs &a, const double *brlen, size_t lds,
-                        hipStream_t s) {
+hipError_t launch_tiles(int precision, int kp, const BatchArgs &a, const double *brlen, size_t lds, hipStream_t s) {
     if (a.n_tiles <= 0) return hipSuccess;
-    dim3 g(a.n_tiles), b(kTileBlock);
-    (void)grad;  // the program decides: one EVAL (lnL) or one per edge (gradient)
-    if (precision == PT_FP32)
-        hipLaunchKernelGGL((k_tiles<float, kTileBlock, kTileItems>), g, b, lds, s, a, brlen);
-    else
-        hipLaunchKernelGGL((k_tiles<double, kTileBlock, kTileItems>), g, b, lds, s, a, brlen);
-    return hipGetLastError();
+    PT_KP_SWITCH(return precision == PT_FP32 ? launch_tiles_t<float, kTileBlock, KP>(a, brlen, lds, s)
+                                             : launch_tiles_t<double, kTileBlock, KP>(a, brlen, lds, s));
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_reduce(bool grad, const BatchArgs &a, double *lnl, double *gout, double *hout,

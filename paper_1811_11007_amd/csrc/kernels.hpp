@@ -18,28 +18,39 @@ struct BatchArgs {
     uint16_t *cnt;
     double *pmat;               // [sum_b E_b * Kp_b * 16]
     double *part;               // tile partial sums [tile][part_cols][3]
+    void *tab;                  // optimisation: per-block eigenbasis tables when not in LDS
     int32_t *queue;             // optimisation work counter
     int32_t n_trees;
     int32_t n_tiles;
     int64_t n_edges;            // total flat edges
     int32_t part_cols;
+    int32_t kp;                 // padded category count of every layout in the batch
+    long long *prof;            // optimisation: per-tree phase counters [n_trees][8], or null
 };
 
-// Items per tile of the tile kernels (threads per block x items per thread).
-constexpr int kTileBlock = 256;
-constexpr int kTileItems = 2;
+// Per-tree optimisation counters (when BatchArgs::prof is set).
+enum : int { PROF_PASSES, PROF_EDGE_STEPS, PROF_NEWTON_ITERS, PROF_UPDATES, PROF_CYC_UPDATE,
+             PROF_CYC_TABLE, PROF_CYC_ITERS, PROF_CYC_TOTAL, PROF_FIELDS };
 
+// Patterns per tile of the tile kernels (threads per block x patterns per thread).
+constexpr int kTileBlock = 256;
+constexpr int kTileItems = 1;
+
+// Optimisation kernel shapes: threads per block 256 or 512, patterns per
+// thread 1..64 (a runtime loop bound); kp = padded categories 1, 2, 4, 8.
 bool optimize_shape_supported(int block, int items);
-int optimize_blocks_per_cu(int precision, int block, int items, size_t lds_bytes);
+int optimize_blocks_per_cu(int precision, int block, int kp, bool tab_lds, size_t lds_bytes);
+// Private (spill) bytes per thread of an optimisation kernel instantiation.
+size_t optimize_spill_bytes(int precision, int block, int kp, bool tab_lds);
 
 hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
 hipError_t launch_pmat(const BatchArgs &a, const double *brlen, hipStream_t s);
-hipError_t launch_tiles(int precision, bool grad, const BatchArgs &a, const double *brlen,
+hipError_t launch_tiles(int precision, int kp, const BatchArgs &a, const double *brlen,
                         size_t lds_bytes, hipStream_t s);
 hipError_t launch_reduce(bool grad, const BatchArgs &a, double *lnl, double *grad_out,
                          double *hess_out, hipStream_t s);
-hipError_t launch_optimize(int precision, int block, int items, int grid, const BatchArgs &a,
-                           double *brlen, const OptParams &opt, double *lnl, int32_t *passes,
-                           int32_t *status, size_t lds_bytes, hipStream_t s);
+hipError_t launch_optimize(int precision, int block, int kp, int items, bool tab_lds, int pm_doubles, int grid,
+                           const BatchArgs &a, double *brlen, const OptParams &opt, double *lnl,
+                           int32_t *passes, int32_t *status, size_t lds_bytes, hipStream_t s);
 
 }  // namespace pt

@@ -7,7 +7,8 @@
 // S = V diag(lam) V^T, which gives P(t) = U diag(exp(lam t)) Uinv with
 // U = Pi^-1/2 V and Uinv = V^T Pi^1/2.  The kernels only ever need U, Uinv and
 // lam: transition matrices, their derivatives and the per-edge eigenbasis
-// tables all follow from them.
+// tables all follow from them.  Both sides of an edge project onto the
+// eigenbasis with the same matrix W = Pi^1/2 V (W_im = pi_i U_im = Uinv_mi).
 //
 // Discrete Gamma rate variation (Yang 1994, category means): K categories of
 // probability 1/K cut at the quantiles of Gamma(alpha, rate alpha); the rate
@@ -167,6 +168,7 @@ pt_status build_model(const pt_model &m, AlnDev &d, std::string &err) {
         for (int k = 0; k < 4; ++k) {
             d.U[i * 4 + k] = V[i][k] / sq[i];
             d.Uinv[k * 4 + i] = V[i][k] * sq[i];
+            d.W[i * 4 + k] = V[i][k] * sq[i];
         }
     for (int k = 0; k < 4; ++k) d.lam[k] = lam[k];
     for (int i = 0; i < 4; ++i) d.freqs[i] = m.freqs[i];

@@ -1,14 +1,14 @@
 // pt_device.hpp -- descriptors shared by the host runtime and the kernels.
 //
 // Device memory layout of one batch ("plan"):
-//   partials  T[slot][item][4]   item = pattern * Kp + category, Kp = the
-//             category count padded to a power of two; a tree owns
-//             3 (n-2) directional slots (one per internal node and neighbour:
-//             the partial of that node's side of the edge to the neighbour).
+//   partials  T[slot][Kp][pattern][4]  Kp = the largest category count of the
+//             batch padded to a power of two; a tree owns 3 (n-2)
+//             directional slots (one per internal node and neighbour: the
+//             partial of that node's side of the edge to the neighbour).
 //   scalers   uint16[slot][pattern]  power-of-two scaling events.
 //   pmat      double[edge][Kp][4][4] transition matrices P(r_k t_e).
-// Items of one pattern sit in adjacent lanes of a wavefront, so the per-
-// pattern scaling decision and the sum over categories are lane shuffles.
+// A thread owns a pattern and loops over its categories; for a fixed
+// category, consecutive patterns are consecutive 16- or 32-byte rows.
 #pragma once
 #include <stdint.h>
 
@@ -28,7 +28,8 @@ struct Op {
     int32_t code;
     int32_t dst;    // UPDATE: destination slot;  NEWTON/EVAL: edge
     int32_t a;      // side a
-    int32_t ea;     // UPDATE: edge of side a;     EVAL: output column
+    int32_t ea;     // UPDATE: edge of side a;  EVAL: output column;
+                    // NEWTON: 1 when this step reports the tree's lnL
     int32_t b;      // side b
     int32_t eb;     // UPDATE: edge of side b
     int32_t pad0, pad1;
@@ -41,6 +42,7 @@ struct AlnDev {
     double freqs[4];
     double U[16];          // P(t) = U diag(exp(lam t)) Uinv
     double Uinv[16];
+    double W[16];          // W_im = pi_i U_im = Uinv_mi = sqrt(pi_i) V_im
     double lam[4];
     double rate[kMaxCats]; // category rates (0 for padded categories)
 };
@@ -57,6 +59,8 @@ struct TreeDev {
     int64_t edge_off;      // first edge in the flat per-edge arrays
     int64_t pm_off;        // first double of this tree's transition matrices
     int32_t tile_begin;    // first global tile index of this tree
+    int32_t op_final;      // FP32 optimisation: FP64 lnL program run at the end
+    int32_t n_final;       //   (slots renumbered densely, see tree.cpp)
     int32_t pad;
 };
 

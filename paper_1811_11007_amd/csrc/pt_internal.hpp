@@ -30,6 +30,10 @@ pt_status build_tree(int n, const int32_t *edges, Tree &t, std::string &err);
 // Programs (sequences of Op) executed by the kernels, one per tree.
 // lnL across one edge: the n-2 updates that make both sides valid, then EVAL.
 void compile_loglik(const Tree &t, std::vector<Op> &ops);
+// The same with the n-2 slots it uses renumbered 0..n-3, so the program fits
+// in two thirds of a tree's partial buffer at twice the element size (the
+// FP64 evaluation that ends an FP32 optimisation reuses the FP32 buffer).
+void compile_loglik_dense(const Tree &t, std::vector<Op> &ops);
 // Every directional partial once, then EVAL on every edge (column = edge).
 void compile_grad(const Tree &t, std::vector<Op> &ops);
 // Smoothing passes over the masked edges in depth-first edge order: before

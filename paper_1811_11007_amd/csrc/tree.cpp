@@ -150,6 +150,26 @@ void compile_loglik(const Tree &t, std::vector<Op> &ops) {
     ops.push_back(edge_op(OP_EVAL, 0, ra, rb, 0));
 }
 
+void compile_loglik_dense(const Tree &t, std::vector<Op> &ops) {
+    std::vector<Op> p;
+    compile_loglik(t, p);
+    std::vector<int> id(t.n_slots(), -1);
+    int next = 0;
+    auto map = [&](int r) { return r < 0 ? r : id[r]; };
+    for (Op op : p) {
+        if (op.code == OP_UPDATE) {
+            op.a = map(op.a);
+            op.b = map(op.b);
+            id[op.dst] = next++;
+            op.dst = id[op.dst];
+        } else {
+            op.a = map(op.a);
+            op.b = map(op.b);
+        }
+        ops.push_back(op);
+    }
+}
+
 void compile_grad(const Tree &t, std::vector<Op> &ops) {
     Slots s(t);
     s.out = &ops;
@@ -190,6 +210,8 @@ void compile_optimize(const Tree &t, const uint8_t *mask, std::vector<Op> &first
             ops.push_back(edge_op(OP_NEWTON, e, ra, rb, 0));
             s.touch(e);
         }
+        // the last edge step of a pass also reports the tree's lnL
+        if (!ops.empty()) ops.back().ea = 1;
     };
     pass(first);
     // The validity pattern after a pass is the same for every pass that

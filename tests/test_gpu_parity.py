@@ -169,3 +169,43 @@ def test_gradient_vs_oracle(ctx):
     assert np.max(np.abs(h - hw) / np.maximum(1, np.abs(hw))) < 1e-7
     l32, g32, _ = pt.pt_batch_branch_grad(ctx, [A], pt.Trees([edges]), brlen, pt.PT_FP32)
     assert np.max(np.abs(g32 - gw) / np.maximum(1, np.abs(gw))) < 1e-3
+
+
+def test_optimize_c2_full_batch_as_benchmarked(ctx):
+    """All 48 neighbours of the stored hill-climbed tree in one plan, in the
+    launch configuration the benchmark times (autotuned shape, HIP graph),
+    against the oracle optima stored by tests/golden/make_c2.py."""
+    import json
+    import torch
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "c2_hillclimb.json")))
+    rng = np.random.default_rng(g["seed"])
+    e, b = synth.yule_tree(g["n_taxa"], rng, mean=0.05)
+    aln = synth.make_alignment(e, b, g["n_taxa"], g["n_sites"], rng, alpha=0.5, n_cats=4)
+    n = g["n_taxa"]
+    A = pt.Alignment.from_synth(ctx, aln)
+    want = {tuple(int(x) for x in nb["key"]): nb["lnl"] for nb in g["neighbours"]}
+    ne, nbl, _ = pt.pt_nni_neighbors(n, np.asarray(g["base_edges"], np.int32), np.asarray(g["base_brlen"]))
+    W = (n + 63) // 64
+    keys = [tuple(sum(int(r[w]) << (64 * w) for w in range(W)) for r in pt.pt_topology_key(n, x)) for x in ne]
+    ref = np.array([want[k] for k in keys])
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream()
+    for prec, tol in ((pt.PT_FP32, FP32_ABS), (pt.PT_FP64, None)):
+        plan = pt.Plan(ctx, [A], pt.Trees(list(ne)), pt.PT_PLAN_OPTIMIZE, prec)
+        b0 = torch.tensor(nbl.ravel(), dtype=torch.float64, device=dev)
+        bb = torch.empty_like(b0)
+        lnl = torch.zeros(len(ne), dtype=torch.float64, device=dev)
+        with torch.cuda.stream(stream):
+            plan.autotune(b0)
+            plan.set_graphs(True)
+            for rep in range(3):   # replays of one captured graph
+                bb.copy_(b0, non_blocking=True)
+                plan.optimize(bb, lnl, stream=stream)
+                stream.synchronize()
+                got = lnl.cpu().numpy()
+                say("C2 batch prec", prec, "rep", rep, "max abs", np.max(np.abs(got - ref)))
+                if tol is None:
+                    assert np.max(np.abs(got - ref) / np.abs(ref)) < FP64_REL
+                else:
+                    assert np.max(np.abs(got - ref)) < tol
+        plan.close()
