@@ -120,16 +120,39 @@ __device__ inline double recip(double x) {
     return r;
 }
 
+// Moves a double across lanes with a DPP row shift; lanes whose source lies
+// outside their row of 16 receive 0.
+template <int CTRL>
+__device__ inline double dpp_shr(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ inline double lane_value(double v, int lane) {
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), lane),
+                            __builtin_amdgcn_readlane(__double2loint(v), lane));
+}
+
+// Wavefront sum in a fixed order: a prefix sum inside each row of 16 lanes
+// (DPP row shifts by 1, 2, 4, 8), then the four row totals in row order.
+// Every lane receives the total.
+__device__ inline double wave_sum(double v) {
+    v += dpp_shr<0x111>(v);
+    v += dpp_shr<0x112>(v);
+    v += dpp_shr<0x114>(v);
+    v += dpp_shr<0x118>(v);
+    return (lane_value(v, 15) + lane_value(v, 31)) + (lane_value(v, 47) + lane_value(v, 63));
+}
+
 // Fixed-order block sum of three values; every thread receives the totals.
 // `red` holds two buffers used alternately, so back-to-back sums need one
 // barrier each.
 template <int BS>
 __device__ inline void block_sum3(double &a, double &b, double &c, double *red, int &parity) {
-    for (int m = 32; m >= 1; m >>= 1) {
-        a += __shfl_xor(a, m, 64);
-        b += __shfl_xor(b, m, 64);
-        c += __shfl_xor(c, m, 64);
-    }
+    a = wave_sum(a);
+    b = wave_sum(b);
+    c = wave_sum(c);
     constexpr int W = BS / 64;
     double *r = red + parity * W * 3;
     const int wave = threadIdx.x >> 6;
