@@ -1,0 +1,287 @@
+"""GPU tests of the batching and differentiation extensions and of the ABI's
+plan, graph, mask, arena-cap and error behaviour, against the FP64 oracle.
+
+Workload shapes: 256 trees of 50 taxa x 1500 sites GTR+G4 (gradients),
+512 topologies over four uneven alignments 27x1949, 36x1812, 50x1133,
+64x1008 (batched optimisation), small trees for the edge cases.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import paper_1811_11007_amd as pt
+import synth
+from oracle import core as oc
+from oracle import topo
+
+pytestmark = pytest.mark.gpu
+
+FP32_ABS = 1e-4
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = pt.Context(0)
+    yield c
+    c.close()
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def c4_inputs(n_trees=256):
+    """50 taxa x 1500 sites GTR+G4; topologies from an NNI walk around the
+    generating tree, lengths ~ Exp(mean 0.05)."""
+    rng = np.random.default_rng(4)
+    e, b = synth.yule_tree(50, rng, mean=0.05)
+    aln = synth.make_alignment(e, b, 50, 1500, rng, alpha=0.5, n_cats=4)
+    tops = [x for x, _ in synth.nni_bfs(e, b, 50, n_trees)]
+    lens = rng.exponential(0.05, size=(n_trees, 97))
+    return aln, tops, lens
+
+
+def test_autograd_c4_against_oracle(ctx):
+    import torch
+    from paper_1811_11007_amd.autograd import TreeLogLik
+    aln, tops, lens = c4_inputs()
+    A = pt.Alignment.from_synth(ctx, aln)
+    T = pt.Trees(tops)
+    dev = torch.device("cuda:0")
+    f32 = TreeLogLik(ctx, [A], T, pt.PT_FP32).to(dev)
+    b = torch.tensor(lens.ravel(), dtype=torch.float64, device=dev, requires_grad=True)
+    lnl = f32(b)
+    lnl.sum().backward()
+    g = b.grad.cpu().numpy().reshape(256, 97)
+    l = lnl.detach().cpu().numpy()
+    D = oc.Data.from_alignment(aln)
+    for i in (0, 101, 255):
+        lw, gw, _ = oc.gradient(D, tops[i], lens[i])
+        say("C4 tree", i, "dlnL", l[i] - lw, "max grad err", np.max(np.abs(g[i] - gw) / np.maximum(1, np.abs(gw))))
+        assert abs(l[i] - lw) < FP32_ABS
+        assert np.max(np.abs(g[i] - gw) / np.maximum(1.0, np.abs(gw))) < 1e-3
+    # FP64 path against central differences of the FP64 oracle (h = 1e-5)
+    f64 = TreeLogLik(ctx, [A], T, pt.PT_FP64).to(dev)
+    b64 = torch.tensor(lens.ravel(), dtype=torch.float64, device=dev, requires_grad=True)
+    f64(b64)[7].backward()
+    g64 = b64.grad.cpu().numpy().reshape(256, 97)
+    assert np.all(g64[np.arange(256) != 7] == 0.0)
+    h = 1e-5
+    fd = np.zeros(97)
+    for e in range(97):
+        bp, bm = lens[7].copy(), lens[7].copy()
+        bp[e] += h
+        bm[e] -= h
+        fd[e] = (oc.loglik(D, tops[7], bp) - oc.loglik(D, tops[7], bm)) / (2 * h)
+    say("C4 fp64 vs FD max", np.max(np.abs(g64[7] - fd) / np.maximum(1, np.abs(fd))))
+    # central differences carry O(h^2 |t'''|) truncation error, largest on the
+    # shortest, most curved branches; the analytic oracle gradient is exact
+    assert np.max(np.abs(g64[7] - fd) / np.maximum(1.0, np.abs(fd))) < 1e-4
+    _, gw, _ = oc.gradient(D, tops[7], lens[7])
+    assert np.max(np.abs(g64[7] - gw) / np.maximum(1.0, np.abs(gw))) < 1e-9
+
+
+def test_autograd_gradcheck(ctx):
+    import torch
+    from paper_1811_11007_amd.autograd import PTLogLik
+    rng = np.random.default_rng(40)
+    trees, alns = [], []
+    e, b = synth.yule_tree(8, rng, mean=0.1)
+    aln = synth.make_alignment(e, b, 8, 150, rng, alpha=0.5, n_cats=4)
+    A = pt.Alignment.from_synth(ctx, aln)
+    tops = [e] + [x for x, _ in synth.nni_bfs(e, b, 8, 2)]
+    T = pt.Trees(tops)
+    plan = pt.Plan(ctx, [A], T, pt.PT_PLAN_GRAD, pt.PT_FP64)
+    edge_tree = torch.repeat_interleave(torch.arange(3), torch.tensor([13, 13, 13])).cuda()
+    x = torch.tensor(rng.exponential(0.1, 39) + 0.01, dtype=torch.float64, device="cuda", requires_grad=True)
+    assert torch.autograd.gradcheck(lambda y: PTLogLik.apply(y, plan, edge_tree), (x,), eps=1e-6, atol=1e-4,
+                                    rtol=1e-5)
+
+
+def c3_inputs():
+    import bench
+    return bench.c3_inputs()
+
+
+def test_c3_batched_optimisation(ctx):
+    """512 topologies over four uneven alignments in one persistent launch
+    (autotuned, replayed from a HIP graph)."""
+    import torch
+    alns, trees, lens, idx = c3_inputs()
+    A = [pt.Alignment.from_synth(ctx, a) for a in alns]
+    T = pt.Trees(trees, idx)
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream()
+    start = pt.pt_batch_loglik(ctx, A, T, lens, pt.PT_FP64)
+    res = {}
+    for prec in (pt.PT_FP32, pt.PT_FP64):
+        plan = pt.Plan(ctx, A, T, pt.PT_PLAN_OPTIMIZE, prec)
+        b0 = torch.tensor(lens, dtype=torch.float64, device=dev)
+        b = torch.empty_like(b0)
+        lnl = torch.zeros(T.n_trees, dtype=torch.float64, device=dev)
+        st = torch.zeros(T.n_trees, dtype=torch.int32, device=dev)
+        with torch.cuda.stream(stream):
+            plan.autotune(b0)
+            plan.set_graphs(True)
+            b.copy_(b0, non_blocking=True)
+            plan.optimize(b, lnl, d_status=st, stream=stream)
+            stream.synchronize()
+        res[prec] = (lnl.cpu().numpy(), b.cpu().numpy(), st.cpu().numpy())
+        plan.close()
+    l32, b32, s32 = res[pt.PT_FP32]
+    l64, b64, s64 = res[pt.PT_FP64]
+    say("C3 converged", int((s32 == 0).sum()), int((s64 == 0).sum()), "max |fp32-fp64|", np.max(np.abs(l32 - l64)))
+    assert np.all(s32 == 0) and np.all(s64 == 0)
+    assert np.all(l64 >= start - 1e-6)
+    assert np.max(np.abs(l32 - l64)) < FP32_ABS
+    # the reported lnL is the lnL at the reported lengths
+    at = pt.pt_batch_loglik(ctx, A, T, b64, pt.PT_FP64)
+    assert np.max(np.abs(at - l64) / np.abs(l64)) < 1e-12
+    # oracle on one topology of each of the two smaller alignments
+    offs = T.edge_offset
+    for i in (5, 130):
+        D = oc.Data.from_alignment(alns[idx[i]])
+        want = oc.optimize(D, trees[i], lens[offs[i]:offs[i + 1]])[0]
+        say("C3 tree", i, "oracle", want, "fp64", l64[i] - want, "fp32", l32[i] - want)
+        assert abs(l64[i] - want) < 1e-6 * abs(want)
+        assert abs(l32[i] - want) < FP32_ABS
+
+
+def test_graph_replays_match_eager(ctx):
+    import torch
+    rng = np.random.default_rng(41)
+    e, b = synth.yule_tree(20, rng, mean=0.08)
+    aln = synth.make_alignment(e, b, 20, 600, rng, alpha=0.5, n_cats=4)
+    A = pt.Alignment.from_synth(ctx, aln)
+    tops = [x for x, _ in synth.nni_bfs(e, b, 20, 24)]
+    T = pt.Trees(tops)
+    lens = np.tile(b, 24)
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream()
+    for kind in ("optimize", "loglik", "grad"):
+        k = {"optimize": pt.PT_PLAN_OPTIMIZE, "loglik": pt.PT_PLAN_LOGLIK, "grad": pt.PT_PLAN_GRAD}[kind]
+        plan = pt.Plan(ctx, [A], T, k, pt.PT_FP32)
+        b0 = torch.tensor(lens, dtype=torch.float64, device=dev)
+        # one set of buffers, so the second and later graph calls replay the
+        # graph captured by the first
+        bb = torch.empty_like(b0)
+        lnl = torch.zeros(24, dtype=torch.float64, device=dev)
+        g = torch.zeros_like(b0)
+        outs = []
+        for graphs in (False, True, True, True):
+            plan.set_graphs(graphs)
+            with torch.cuda.stream(stream):
+                bb.copy_(b0, non_blocking=True)
+                lnl.zero_()
+                g.zero_()
+                if kind == "optimize":
+                    plan.optimize(bb, lnl, stream=stream)
+                elif kind == "loglik":
+                    plan.loglik(bb, lnl, stream=stream)
+                else:
+                    plan.grad(bb, lnl, g, stream=stream)
+                stream.synchronize()
+            # eager work of the program's own between replays
+            junk = torch.randn(4096, device=dev).sum().item()
+            outs.append((lnl.cpu().numpy().copy(), bb.cpu().numpy().copy(), g.cpu().numpy().copy()))
+        for o in outs[1:]:
+            for x, y in zip(o, outs[0]):
+                assert np.array_equal(x, y), kind
+        plan.close()
+
+
+def test_arena_cap_splits_batches_identically(ctx, monkeypatch):
+    rng = np.random.default_rng(42)
+    e, b = synth.yule_tree(15, rng, mean=0.08)
+    aln = synth.make_alignment(e, b, 15, 400, rng, alpha=0.5, n_cats=4)
+    A = pt.Alignment.from_synth(ctx, aln)
+    tops = [x for x, _ in synth.nni_bfs(e, b, 15, 10)]
+    T = pt.Trees(tops)
+    lens = np.tile(b, 10)
+    ref = pt.pt_batch_optimize_branches(ctx, [A], T, lens, precision=pt.PT_FP64)
+    refl = pt.pt_batch_loglik(ctx, [A], T, lens, pt.PT_FP64)
+    monkeypatch.setenv("PT_ARENA_CAP_BYTES", str(2 * 1024 * 1024))
+    got = pt.pt_batch_optimize_branches(ctx, [A], T, lens, precision=pt.PT_FP64)
+    gotl = pt.pt_batch_loglik(ctx, [A], T, lens, pt.PT_FP64)
+    assert np.allclose(got[0], ref[0], rtol=1e-12, atol=0)
+    assert np.allclose(got[1], ref[1], rtol=1e-9, atol=1e-12)
+    assert np.allclose(gotl, refl, rtol=1e-13, atol=0)
+    monkeypatch.setenv("PT_ARENA_CAP_BYTES", "1000")
+    with pytest.raises(pt.PTError) as ei:
+        pt.pt_batch_loglik(ctx, [A], T, lens, pt.PT_FP64)
+    assert ei.value.code == -2
+
+
+def test_masked_optimisation_radius0(ctx):
+    """Only the new edge of each NNI neighbour moves (the paper's default
+    proposal step); compared with the oracle under the same mask."""
+    rng = np.random.default_rng(43)
+    e, b = synth.yule_tree(12, rng, mean=0.08)
+    aln = synth.make_alignment(e, b, 12, 500, rng, alpha=0.5, n_cats=4)
+    A = pt.Alignment.from_synth(ctx, aln)
+    ne, nb, touched = pt.pt_nni_neighbors(12, e, b)
+    T = pt.Trees(list(ne))
+    mask = np.zeros((len(ne), 21), np.uint8)
+    mask[np.arange(len(ne)), touched[:, 0]] = 1
+    l, bo, _, st = pt.pt_batch_optimize_branches(ctx, [A], T, nb.ravel(), mask=mask.ravel(), precision=pt.PT_FP64)
+    bo = bo.reshape(len(ne), 21)
+    D = oc.Data.from_alignment(aln)
+    for i in range(len(ne)):
+        keep = mask[i] == 0
+        assert np.array_equal(bo[i][keep], nb[i][keep])
+        want = oc.optimize(D, ne[i], nb[i], mask=mask[i])[0]
+        assert abs(l[i] - want) < 1e-8 * abs(want)
+
+
+def test_small_trees_and_closed_form(ctx):
+    # two taxa, JC69: closed-form optimum
+    N, k = 200, 37
+    tips = np.array([[1] * N, [1] * (N - k) + [2] * k], dtype=np.uint8)
+    tips_c, w = synth.compress(np.log2(tips).astype(np.int8))
+    A = pt.Alignment(ctx, tips_c, w, np.ones(6), np.full(4, 0.25), 1.0, 1)
+    l, b, _, st = pt.pt_batch_optimize_branches(ctx, [A], pt.Trees([[[0, 1]]]), [0.05], precision=pt.PT_FP64)
+    assert abs(b[0] - 0.21243560653793642) < 1e-7
+    assert abs(l[0] - (-413.68575471496695)) < 1e-9
+    # three and four taxa against the oracle
+    for n in (3, 4):
+        rng = np.random.default_rng(44 + n)
+        e, bb = synth.random_tree(n, rng, mean=0.1)
+        aln = synth.make_alignment(e, bb, n, 300, rng, alpha=0.5, n_cats=4)
+        A = pt.Alignment.from_synth(ctx, aln)
+        D = oc.Data.from_alignment(aln)
+        l, _, _, _ = pt.pt_batch_optimize_branches(ctx, [A], pt.Trees([e]), bb, precision=pt.PT_FP64)
+        assert abs(l[0] - oc.optimize(D, e, bb)[0]) < 1e-8
+        g = pt.pt_batch_branch_grad(ctx, [A], pt.Trees([e]), bb, pt.PT_FP64)[1]
+        assert np.max(np.abs(g - oc.gradient(D, e, bb)[1])) < 1e-8
+
+
+def test_abi_errors(ctx):
+    rng = np.random.default_rng(45)
+    e, b = synth.yule_tree(6, rng)
+    aln = synth.make_alignment(e, b, 6, 50, rng)
+    A = pt.Alignment.from_synth(ctx, aln)
+    bad = e.copy()
+    bad[0, 0] = 40
+    for call in (lambda: pt.pt_batch_loglik(ctx, [A], pt.Trees([bad]), b),
+                 lambda: pt.pt_batch_loglik(ctx, [A], pt.Trees([e]), np.where(np.arange(9) == 2, np.nan, b)),
+                 lambda: pt.pt_batch_loglik(ctx, [A], pt.Trees([e]), -b),
+                 lambda: pt.pt_batch_loglik(ctx, [A], pt.Trees([e[:-1]]), b[:-1]),
+                 lambda: pt.pt_batch_loglik(ctx, [A], pt.Trees([e], [1]), b),
+                 lambda: pt.pt_batch_optimize_branches(ctx, [A], pt.Trees([e]), b, mask=np.full(9, 2, np.uint8)),
+                 lambda: pt.Alignment(ctx, np.zeros((6, 3), np.uint8), np.ones(3), np.ones(6), np.full(4, .25)),
+                 lambda: pt.Alignment(ctx, aln.tips, -aln.weights, np.ones(6), np.full(4, .25))):
+        with pytest.raises(pt.PTError) as ei:
+            call()
+        assert ei.value.code == -1, ei.value
+    o = pt.opt_default(pt.PT_FP64)
+    o.t_min = 0.0
+    with pytest.raises(pt.PTError):
+        pt.pt_batch_optimize_branches(ctx, [A], pt.Trees([e]), b, opt=o)
+    # non-convergence is reported, not an error
+    o = pt.opt_default(pt.PT_FP64)
+    o.max_passes = 1
+    _, _, ps, st = pt.pt_batch_optimize_branches(ctx, [A], pt.Trees([e]), b, opt=o)
+    assert ps[0] == 1 and st[0] == 1
+    # empty batch
+    assert len(pt.pt_batch_loglik(ctx, [A], pt.Trees([]), np.zeros(0))) == 0
