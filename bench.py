@@ -81,6 +81,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-extras", action="store_true", help="only the headline measurement")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="first run an elementwise copy of 256 MiB (y = -x, float32) whose known traffic "
+                         "calibrates hardware byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build runs the batch on a single MI355X "
@@ -90,6 +93,13 @@ def main():
 
     import torch
     import paper_1811_11007_amd as pt
+
+    if args.copy_probe:
+        x = torch.ones(64 << 20, dtype=torch.float32, device="cuda:0")
+        y = torch.neg(x)
+        torch.cuda.synchronize()
+        log("copy probe: %d bytes read, %d bytes written" % (x.numel() * 4, y.numel() * 4))
+        del x, y
 
     g, aln = c2_inputs()
     n = g["n_taxa"]

@@ -232,6 +232,59 @@ pt_status pt_nni_neighbors(int32_t n, const int32_t *edges, const double *brlen,
  * out: uint64[n-3][W].  Equal keys <=> equal unrooted topologies.  n >= 4. */
 pt_status pt_topology_key(int32_t n, const int32_t *edges, uint64_t *out);
 
+/* -------------------------------------------- warm-start network (learned) */
+
+/* Features of every NNI move of a tree whose lengths have been optimised,
+ * in pt_nni_neighbors order, PT_NNI_FEATURES floats each: log t of the five
+ * edges the move touches (central, b, its swap partner, the remaining edge
+ * at u, the remaining edge at v; t floored at 1e-6), log leaf count and
+ * log(clade length + 1e-3) of the four subtrees hanging off the last four,
+ * and log of the total tree length.  out: float[2(n-3)][PT_NNI_FEATURES].
+ * n >= 4.  Host only. */
+#define PT_NNI_FEATURES 14
+pt_status pt_nni_features(int32_t n, const int32_t *edges, const double *brlen, float *out);
+
+/* A two-layer perceptron y = tanh(x W1 + b1) W2 + b2 in FP32, evaluated and
+ * trained (mean squared error, Adam) by the library's own kernels.  It maps
+ * the features of an NNI move to the log-ratio of the five touched edges'
+ * optimised lengths to the parent's lengths, to warm-start the neighbour's
+ * branch optimisation (the search always judges a topology by its fully
+ * optimised lnL, so the network only changes where Newton starts).
+ * Parameters are packed W1[n_in][n_hidden], b1[n_hidden], W2[n_hidden][n_out],
+ * b2[n_out]; `params` (host) gives their initial values.  Device pointers in
+ * the calls below are row-major float arrays; work is enqueued on `stream`
+ * (NULL = null stream).  A call with more rows than any before grows the
+ * network's scratch buffers (an allocation). */
+typedef struct pt_mlp pt_mlp;
+typedef struct {
+    float lr, beta1, beta2, eps;
+} pt_adam;
+pt_status pt_mlp_create(pt_ctx *ctx, int32_t n_in, int32_t n_hidden, int32_t n_out, const float *params,
+                        pt_mlp **out);
+void pt_mlp_destroy(pt_mlp *mlp);
+/* Number of packed parameters. */
+int64_t pt_mlp_param_count(const pt_mlp *mlp);
+pt_status pt_mlp_get_params(pt_mlp *mlp, float *params_out);
+pt_status pt_mlp_set_params(pt_mlp *mlp, const float *params);
+/* d_y[rows][n_out] = network(d_x[rows][n_in]). */
+pt_status pt_mlp_forward(pt_mlp *mlp, const float *d_x, int32_t rows, float *d_y, void *stream);
+/* Gradient of the mean over rows and outputs of (y - target)^2 with respect
+ * to the packed parameters (d_grad, device float[param_count]); d_loss
+ * (device double, NULL ok) receives the sum of squared errors. */
+pt_status pt_mlp_gradient(pt_mlp *mlp, const float *d_x, const float *d_target, int32_t rows, float *d_grad,
+                          double *d_loss, void *stream);
+/* Warm start of NNI neighbours: y = network(d_x) as above, then for every
+ * row r and output o with d_pos[r][o] >= 0,
+ *   d_brlen[d_pos[r][o]] = clamp(max(d_base[r][o], 1e-6) * exp(y[r][o]), t_min, t_max),
+ * i.e. the outputs are log-ratios of a neighbour's lengths to its parent's.
+ * d_pos: device int32[rows][n_out], indices into d_brlen (distinct, in
+ * range: the caller's responsibility); d_base: device double[rows][n_out]. */
+pt_status pt_mlp_warm_start(pt_mlp *mlp, const float *d_x, int32_t rows, const int32_t *d_pos, const double *d_base,
+                            double t_min, double t_max, double *d_brlen, void *stream);
+/* One Adam step on that loss. */
+pt_status pt_mlp_train_step(pt_mlp *mlp, const float *d_x, const float *d_target, int32_t rows,
+                            const pt_adam *opt, double *d_loss, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -78,6 +78,55 @@ def nni_neighbors(edges, brlen, n):
     return res
 
 
+def nni_touched(edges, n):
+    """Per NNI neighbour (nni_neighbors order), the five edges it touches:
+    the central edge, the edge moved from u, the edge of v it swaps with,
+    the edge that stays at u and the edge that stays at v."""
+    edges = np.asarray(edges, dtype=np.int32)
+    adj = _adj(edges, n)
+    out = []
+    for e, (u, v) in enumerate(edges.tolist()):
+        if u < n or v < n:
+            continue
+        eu = [x for (_, x) in adj[u] if x != e]
+        ev = [x for (_, x) in adj[v] if x != e]
+        for k, ec in enumerate(ev):
+            out.append((e, eu[1], ec, eu[0], ev[1 - k]))
+    return out
+
+
+def nni_features(edges, brlen, n):
+    """Warm-start features of every NNI neighbour, from splits alone.
+
+    Per move: log t of the five touched edges (t floored at 1e-6); for the
+    four non-central ones, the log leaf count and log(clade length + 1e-3)
+    of the clade on their side away from the central edge; and the log of
+    the tree length.  The clade of edge x away from the central edge c is
+    the side of x that lies wholly on one side of c; its length sums the
+    edges one of whose sides lies inside it."""
+    edges = np.asarray(edges, dtype=np.int32)
+    brlen = np.asarray(brlen, dtype=np.float64)
+    full = (1 << n) - 1
+    sp = edge_splits(edges, n)
+    sides = [(s, full ^ s) for s in sp]
+    total = float(brlen.sum())
+    rows = []
+    for tt in nni_touched(edges, n):
+        c, cc = sides[tt[0]]
+        f = [np.log(max(brlen[x], 1e-6)) for x in tt]
+        cnt, ln = [], []
+        for x in tt[1:]:
+            clade = [s for s in sides[x] if (s & c) == s or (s & cc) == s]
+            assert len(clade) == 1
+            F = clade[0]
+            inside = sum(brlen[y] for y in range(len(sp))
+                         if y != x and any((s & F) == s for s in sides[y]))
+            cnt.append(np.log(bin(F).count("1")))
+            ln.append(np.log(inside + 1e-3))
+        rows.append(f + cnt + ln + [np.log(total)])
+    return np.array(rows)
+
+
 def all_topologies(n):
     """Every unrooted binary topology on n >= 3 taxa (edge lists)."""
     out = []

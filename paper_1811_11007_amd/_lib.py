@@ -24,8 +24,12 @@ EXPORTS = [
     "pt_opt_default", "pt_batch_loglik", "pt_batch_optimize_branches", "pt_batch_branch_grad",
     "pt_plan_create", "pt_plan_destroy", "pt_plan_set_graphs", "pt_plan_loglik",
     "pt_plan_optimize", "pt_plan_grad", "pt_plan_autotune", "pt_plan_traffic", "pt_plan_set_profile", "pt_plan_info",
-    "pt_model_info", "pt_tree_check", "pt_nni_neighbors", "pt_topology_key",
+    "pt_model_info", "pt_tree_check", "pt_nni_neighbors", "pt_topology_key", "pt_nni_features",
+    "pt_mlp_create", "pt_mlp_destroy", "pt_mlp_param_count", "pt_mlp_get_params", "pt_mlp_set_params",
+    "pt_mlp_forward", "pt_mlp_warm_start", "pt_mlp_gradient", "pt_mlp_train_step",
 ]
+
+PT_NNI_FEATURES = 14
 
 
 class PTError(RuntimeError):
@@ -43,6 +47,11 @@ class pt_trees(ctypes.Structure):
     _fields_ = [("n_trees", ctypes.c_int32), ("aln_index", ctypes.POINTER(ctypes.c_int32)),
                 ("edge_offset", ctypes.POINTER(ctypes.c_int64)),
                 ("edges", ctypes.POINTER(ctypes.c_int32))]
+
+
+class pt_adam(ctypes.Structure):
+    _fields_ = [("lr", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
+                ("eps", ctypes.c_float)]
 
 
 class pt_opt(ctypes.Structure):
@@ -99,6 +108,18 @@ def lib():
         L.pt_tree_check.argtypes = [i32, vp]
         L.pt_nni_neighbors.argtypes = [i32, vp, vp, vp, vp, vp]
         L.pt_topology_key.argtypes = [i32, vp, vp]
+        L.pt_nni_features.argtypes = [i32, vp, vp, vp]
+        L.pt_mlp_create.argtypes = [vp, i32, i32, i32, vp, P(vp)]
+        L.pt_mlp_destroy.argtypes = [vp]
+        L.pt_mlp_destroy.restype = None
+        L.pt_mlp_param_count.argtypes = [vp]
+        L.pt_mlp_param_count.restype = i64
+        L.pt_mlp_get_params.argtypes = [vp, vp]
+        L.pt_mlp_set_params.argtypes = [vp, vp]
+        L.pt_mlp_forward.argtypes = [vp, vp, i32, vp, vp]
+        L.pt_mlp_warm_start.argtypes = [vp, vp, i32, vp, vp, ctypes.c_double, ctypes.c_double, vp, vp]
+        L.pt_mlp_gradient.argtypes = [vp, vp, vp, i32, vp, vp, vp]
+        L.pt_mlp_train_step.argtypes = [vp, vp, vp, i32, P(pt_adam), vp, vp]
         for name in EXPORTS:
             if getattr(L, name).restype is ctypes.c_int:
                 getattr(L, name).restype = i32
@@ -275,6 +296,72 @@ def pt_topology_key(n, edges):
     out = np.zeros((max(n - 3, 0), W), np.uint64)
     check(lib().pt_topology_key(n, _ptr(e), _ptr(out)))
     return out
+
+
+def pt_nni_features(n, edges, brlen):
+    """float32[2(n-3)][PT_NNI_FEATURES] features of each NNI move (pt_nni_neighbors order)."""
+    e = np.ascontiguousarray(edges, dtype=np.int32)
+    b = np.ascontiguousarray(brlen, dtype=np.float64)
+    out = np.zeros((max(2 * (n - 3), 0), PT_NNI_FEATURES), np.float32)
+    check(lib().pt_nni_features(int(n), _ptr(e), _ptr(b), _ptr(out)))
+    return out
+
+
+def _dptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+class MLP:
+    """The warm-start perceptron (pt_mlp_*), driven with torch float32 tensors."""
+
+    def __init__(self, ctx, n_in, n_hidden, n_out, params):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        self.shape = (int(n_in), int(n_hidden), int(n_out))
+        self.h = ctypes.c_void_p()
+        check(lib().pt_mlp_create(ctx.h, *self.shape, _ptr(p), ctypes.byref(self.h)))
+        self.n_params = int(lib().pt_mlp_param_count(self.h))
+
+    def params(self):
+        out = np.zeros(self.n_params, np.float32)
+        check(lib().pt_mlp_get_params(self.h, _ptr(out)))
+        return out
+
+    def set_params(self, params):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        if p.size != self.n_params:
+            raise ValueError("expected %d parameters" % self.n_params)
+        check(lib().pt_mlp_set_params(self.h, _ptr(p)))
+
+    def forward(self, d_x, d_y=None, stream=None):
+        import torch
+        if d_y is None:
+            d_y = torch.empty((d_x.shape[0], self.shape[2]), dtype=torch.float32, device=d_x.device)
+        check(lib().pt_mlp_forward(self.h, _dptr(d_x), int(d_x.shape[0]), _dptr(d_y), Plan._stream(stream)))
+        return d_y
+
+    def warm_start(self, d_x, d_pos, d_base, d_brlen, t_min=1e-8, t_max=100.0, stream=None):
+        check(lib().pt_mlp_warm_start(self.h, _dptr(d_x), int(d_x.shape[0]), _dptr(d_pos), _dptr(d_base),
+                                      float(t_min), float(t_max), _dptr(d_brlen), Plan._stream(stream)))
+
+    def gradient(self, d_x, d_t, d_grad, d_loss=None, stream=None):
+        check(lib().pt_mlp_gradient(self.h, _dptr(d_x), _dptr(d_t), int(d_x.shape[0]), _dptr(d_grad),
+                                    _dptr(d_loss), Plan._stream(stream)))
+
+    def train_step(self, d_x, d_t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, d_loss=None, stream=None):
+        a = pt_adam(lr, beta1, beta2, eps)
+        check(lib().pt_mlp_train_step(self.h, _dptr(d_x), _dptr(d_t), int(d_x.shape[0]), ctypes.byref(a),
+                                      _dptr(d_loss), Plan._stream(stream)))
+
+    def close(self):
+        if self.h:
+            lib().pt_mlp_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Plan:

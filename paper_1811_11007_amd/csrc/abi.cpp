@@ -19,6 +19,7 @@
 #include <vector>
 
 #include "kernels.hpp"
+#include "mlp.hpp"
 #include "pt_internal.hpp"
 
 using pt::AlnDev;
@@ -936,6 +937,149 @@ pt_status pt_topology_key(int32_t n, const int32_t *edges, uint64_t *out) {
     std::string err;
     pt_status st = pt::topology_key(n, edges, out, err);
     return st ? fail(st, err) : PT_OK;
+}
+
+pt_status pt_nni_features(int32_t n, const int32_t *edges, const double *brlen, float *out) {
+    if (!edges || !brlen || !out) return fail(PT_EINVAL, "NULL argument");
+    std::string err;
+    pt_status st = pt::nni_features(n, edges, brlen, out, err);
+    return st ? fail(st, err) : PT_OK;
+}
+
+}  // extern "C"
+
+struct pt_mlp {
+    pt_ctx *ctx = nullptr;
+    int ni = 0, nh = 0, no = 0, np = 0;
+    int64_t step = 0;
+    float *d_p = nullptr, *d_m = nullptr, *d_v = nullptr, *d_g = nullptr;
+    int cap = 0;
+    float *d_h = nullptr, *d_y = nullptr, *d_dy = nullptr, *d_dz = nullptr;
+    double *d_rl = nullptr;
+};
+
+namespace {
+
+void mlp_free_scratch(pt_mlp *m) {
+    for (void *p : {(void *)m->d_h, (void *)m->d_y, (void *)m->d_dy, (void *)m->d_dz, (void *)m->d_rl})
+        if (p) (void)hipFree(p);
+    m->d_h = m->d_y = m->d_dy = m->d_dz = nullptr;
+    m->d_rl = nullptr;
+    m->cap = 0;
+}
+
+pt_status mlp_scratch(pt_mlp *m, int rows) {
+    if (rows <= m->cap) return PT_OK;
+    mlp_free_scratch(m);
+    const size_t r = (size_t)rows;
+    PT_HIP(hipMalloc(&m->d_h, sizeof(float) * r * m->nh));
+    PT_HIP(hipMalloc(&m->d_dz, sizeof(float) * r * m->nh));
+    PT_HIP(hipMalloc(&m->d_y, sizeof(float) * r * m->no));
+    PT_HIP(hipMalloc(&m->d_dy, sizeof(float) * r * m->no));
+    PT_HIP(hipMalloc(&m->d_rl, sizeof(double) * r));
+    m->cap = rows;
+    return PT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pt_status pt_mlp_create(pt_ctx *ctx, int32_t n_in, int32_t n_hidden, int32_t n_out, const float *params,
+                        pt_mlp **out) {
+    if (!ctx || !params || !out) return fail(PT_EINVAL, "NULL argument");
+    if (n_in < 1 || n_hidden < 1 || n_out < 1 || n_in > 4096 || n_hidden > 4096 || n_out > 4096)
+        return fail(PT_EINVAL, "layer sizes must be in 1..4096");
+    std::unique_ptr<pt_mlp> m(new pt_mlp);
+    m->ctx = ctx;
+    m->ni = n_in;
+    m->nh = n_hidden;
+    m->no = n_out;
+    m->np = n_in * n_hidden + n_hidden + n_hidden * n_out + n_out;
+    for (int i = 0; i < m->np; ++i)
+        if (!std::isfinite(params[i])) return fail(PT_EINVAL, "parameters must be finite");
+    PT_HIP(hipSetDevice(ctx->device));
+    const size_t b = sizeof(float) * m->np;
+    PT_HIP(hipMalloc(&m->d_p, b));
+    PT_HIP(hipMalloc(&m->d_m, b));
+    PT_HIP(hipMalloc(&m->d_v, b));
+    PT_HIP(hipMalloc(&m->d_g, b));
+    PT_HIP(hipMemcpy(m->d_p, params, b, hipMemcpyHostToDevice));
+    PT_HIP(hipMemset(m->d_m, 0, b));
+    PT_HIP(hipMemset(m->d_v, 0, b));
+    *out = m.release();
+    return PT_OK;
+}
+
+void pt_mlp_destroy(pt_mlp *mlp) {
+    if (!mlp) return;
+    mlp_free_scratch(mlp);
+    for (void *p : {(void *)mlp->d_p, (void *)mlp->d_m, (void *)mlp->d_v, (void *)mlp->d_g})
+        if (p) (void)hipFree(p);
+    delete mlp;
+}
+
+int64_t pt_mlp_param_count(const pt_mlp *mlp) { return mlp ? mlp->np : 0; }
+
+pt_status pt_mlp_get_params(pt_mlp *mlp, float *params_out) {
+    if (!mlp || !params_out) return fail(PT_EINVAL, "NULL argument");
+    PT_HIP(hipMemcpy(params_out, mlp->d_p, sizeof(float) * mlp->np, hipMemcpyDeviceToHost));
+    return PT_OK;
+}
+
+pt_status pt_mlp_set_params(pt_mlp *mlp, const float *params) {
+    if (!mlp || !params) return fail(PT_EINVAL, "NULL argument");
+    PT_HIP(hipMemcpy(mlp->d_p, params, sizeof(float) * mlp->np, hipMemcpyHostToDevice));
+    return PT_OK;
+}
+
+pt_status pt_mlp_forward(pt_mlp *mlp, const float *d_x, int32_t rows, float *d_y, void *stream) {
+    if (!mlp || rows < 0 || (rows > 0 && (!d_x || !d_y))) return fail(PT_EINVAL, "bad arguments");
+    pt_status st = mlp_scratch(mlp, rows);
+    if (st) return st;
+    PT_HIP(pt::mlp_forward(d_x, mlp->d_p, rows, mlp->ni, mlp->nh, mlp->no, mlp->d_h, d_y, (hipStream_t)stream));
+    return PT_OK;
+}
+
+pt_status pt_mlp_warm_start(pt_mlp *mlp, const float *d_x, int32_t rows, const int32_t *d_pos, const double *d_base,
+                            double t_min, double t_max, double *d_brlen, void *stream) {
+    if (!mlp || rows < 0 || (rows > 0 && (!d_x || !d_pos || !d_base || !d_brlen)))
+        return fail(PT_EINVAL, "bad arguments");
+    if (!(t_min > 0.0) || !(t_max > t_min)) return fail(PT_EINVAL, "need 0 < t_min < t_max");
+    pt_status st = mlp_scratch(mlp, rows);
+    if (st) return st;
+    hipStream_t s = (hipStream_t)stream;
+    PT_HIP(pt::mlp_forward(d_x, mlp->d_p, rows, mlp->ni, mlp->nh, mlp->no, mlp->d_h, mlp->d_y, s));
+    PT_HIP(pt::mlp_warm_apply(mlp->d_y, d_pos, d_base, rows, mlp->no, t_min, t_max, d_brlen, s));
+    return PT_OK;
+}
+
+pt_status pt_mlp_gradient(pt_mlp *mlp, const float *d_x, const float *d_target, int32_t rows, float *d_grad,
+                          double *d_loss, void *stream) {
+    if (!mlp || rows < 1 || !d_x || !d_target || !d_grad) return fail(PT_EINVAL, "bad arguments");
+    pt_status st = mlp_scratch(mlp, rows);
+    if (st) return st;
+    hipStream_t s = (hipStream_t)stream;
+    PT_HIP(pt::mlp_forward(d_x, mlp->d_p, rows, mlp->ni, mlp->nh, mlp->no, mlp->d_h, mlp->d_y, s));
+    PT_HIP(pt::mlp_loss_grad(mlp->d_y, d_target, rows, mlp->no, mlp->d_dy, mlp->d_rl, d_loss, s));
+    PT_HIP(pt::mlp_backward(d_x, mlp->d_p, mlp->d_h, mlp->d_dy, rows, mlp->ni, mlp->nh, mlp->no, mlp->d_dz, d_grad,
+                            s));
+    return PT_OK;
+}
+
+pt_status pt_mlp_train_step(pt_mlp *mlp, const float *d_x, const float *d_target, int32_t rows, const pt_adam *opt,
+                            double *d_loss, void *stream) {
+    if (!opt || !(opt->lr > 0.0f) || !(opt->beta1 >= 0.0f && opt->beta1 < 1.0f) ||
+        !(opt->beta2 >= 0.0f && opt->beta2 < 1.0f) || !(opt->eps > 0.0f))
+        return fail(PT_EINVAL, "bad Adam settings");
+    pt_status st = pt_mlp_gradient(mlp, d_x, d_target, rows, mlp ? mlp->d_g : nullptr, d_loss, stream);
+    if (st) return st;
+    mlp->step += 1;
+    const float c1 = 1.0f - std::pow(opt->beta1, (float)mlp->step);
+    const float c2 = 1.0f - std::pow(opt->beta2, (float)mlp->step);
+    PT_HIP(pt::mlp_adam(mlp->d_p, mlp->d_g, mlp->d_m, mlp->d_v, mlp->np, opt->lr, opt->beta1, opt->beta2, opt->eps,
+                        c1, c2, (hipStream_t)stream));
+    return PT_OK;
 }
 
 }  // extern "C"

@@ -46,5 +46,6 @@ void compile_optimize(const Tree &t, const uint8_t *mask, std::vector<Op> &first
 pt_status nni_neighbors(int n, const int32_t *edges, const double *brlen, int32_t *out_edges,
                         double *out_brlen, int32_t *out_touched, std::string &err);
 pt_status topology_key(int n, const int32_t *edges, uint64_t *out, std::string &err);
+pt_status nni_features(int n, const int32_t *edges, const double *brlen, float *out, std::string &err);
 
 }  // namespace pt

@@ -9,6 +9,7 @@
 // branch optimisation need.  The compiler simulates which slots a length
 // change invalidates and emits exactly the updates each step needs.
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <functional>
 
@@ -262,6 +263,60 @@ pt_status nni_neighbors(int n, const int32_t *edges, const double *brlen, int32_
                 tt[0] = e; tt[1] = eb; tt[2] = ec; tt[3] = eu[0]; tt[4] = ev[1 - w];
             }
         }
+    }
+    return PT_OK;
+}
+
+namespace {
+
+// Leaf count and total edge length of the subtree hanging from `node` away
+// from `from`.
+void clade(const Tree &t, const double *brlen, int node, int from, int &leaves, double &len) {
+    if (node < t.n) {
+        leaves += 1;
+        return;
+    }
+    for (int j = 0; j < 3; ++j) {
+        const int c = t.nbr[3 * node + j];
+        if (c == from) continue;
+        len += brlen[t.nedge[3 * node + j]];
+        clade(t, brlen, c, node, leaves, len);
+    }
+}
+
+}  // namespace
+
+pt_status nni_features(int n, const int32_t *edges, const double *brlen, float *out, std::string &err) {
+    if (n < 4) { err = "NNI needs n >= 4"; return PT_EINVAL; }
+    Tree t;
+    pt_status st = build_tree(n, edges, t, err);
+    if (st) return st;
+    const int E = t.n_edges;
+    std::vector<int32_t> ne((size_t)2 * (n - 3) * 2 * E);
+    std::vector<int32_t> touched((size_t)2 * (n - 3) * 5);
+    st = nni_neighbors(n, edges, nullptr, ne.data(), nullptr, touched.data(), err);
+    if (st) return st;
+    double total = 0.0;
+    for (int e = 0; e < E; ++e) total += brlen[e];
+    auto lt = [](double x) { return (float)std::log(std::max(x, 1e-6)); };
+    for (int k = 0; k < 2 * (n - 3); ++k) {
+        const int32_t *tt = touched.data() + (size_t)k * 5;
+        float *f = out + (size_t)k * 14;
+        const int ce = tt[0];
+        const int u = edges[2 * ce], v = edges[2 * ce + 1];
+        for (int q = 0; q < 5; ++q) f[q] = lt(brlen[tt[q]]);
+        for (int q = 1; q < 5; ++q) {
+            // the end of edge tt[q] away from the central edge
+            const int x0 = edges[2 * tt[q]], x1 = edges[2 * tt[q] + 1];
+            const int near = (x0 == u || x0 == v) ? x0 : x1;
+            const int far = near == x0 ? x1 : x0;
+            int leaves = 0;
+            double len = 0.0;
+            clade(t, brlen, far, near, leaves, len);
+            f[4 + q] = (float)std::log((double)leaves);
+            f[8 + q] = (float)std::log(len + 1e-3);
+        }
+        f[13] = (float)std::log(total);
     }
     return PT_OK;
 }

@@ -1,0 +1,198 @@
+"""Threshold search over NNI neighbourhoods with batched GPU optimisation.
+
+The search follows the topographer's loop (Methods, "Phylogenetic
+Topographer"): a FIFO todo queue of candidate topologies, a visited table of
+every topology whose branch lengths were fully optimised, and a good table
+of those whose optimised lnL is at least lmax + T (T < 0).  Visiting a
+topology optimises all its lengths; a good topology proposes each of its
+unvisited NNI neighbours, whose lengths are partially optimised (radius 0:
+the new edge only; radius -1: all edges) and which join the queue when that
+partial lnL is at least lmax + T.  Every judgement of a topology as good
+uses its fully optimised lnL.
+
+Batching: the queue is consumed a batch at a time, so one batch of visits
+and one batch of proposals are each a single persistent launch of the
+library's optimiser.  lmax is updated after each batch, and the good table
+is filtered by the final lmax + T at the end, so the result does not depend
+on the batch size beyond what the paper's own order dependence allows.
+
+Topology identity is the library's canonical split key (sorted non-trivial
+splits as bitmasks), hashed on the host in Python sets and dicts.
+
+Starting lengths of a proposal are its parent's lengths carried through the
+move (cold start) or, with a warm start, the parent's lengths with the five
+edges the move touches replaced by the network's prediction.  A queued
+proposal carries its partially optimised lengths to its visit.
+"""
+from __future__ import annotations
+
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import _lib as L
+
+
+@dataclass
+class SearchResult:
+    lmax: float
+    good: dict  # key bytes -> (lnL, edges, brlen)
+    visited: int
+    proposed: int
+    queued: int
+    full_passes: int
+    full_time_s: float
+    proposal_time_s: float
+    batches: int
+    samples: list = field(default_factory=list)  # (features, targets) arrays, when collecting
+
+
+class WarmStart:
+    """A trained network that predicts the five touched lengths of a move."""
+
+    def __init__(self, ctx, params, n_hidden=128):
+        self.net = L.MLP(ctx, L.PT_NNI_FEATURES, n_hidden, 5, params)
+
+    @classmethod
+    def load(cls, ctx, path):
+        import json
+        d = json.load(open(path))
+        return cls(ctx, np.asarray(d["params"], np.float32), d["n_hidden"])
+
+
+class ThresholdSearch:
+    def __init__(self, ctx, aln, threshold=-10.0, radius=0, warm: WarmStart | None = None,
+                 precision=L.PT_FP32, batch=1024, opt=None):
+        if threshold >= 0:
+            raise ValueError("the threshold offset T must be negative")
+        if radius not in (0, -1):
+            raise ValueError("radius must be 0 (new edge only) or -1 (all edges)")
+        self.ctx, self.aln, self.T, self.radius, self.warm = ctx, aln, float(threshold), radius, warm
+        self.precision, self.batch = precision, int(batch)
+        self.opt = opt if opt is not None else L.opt_default(precision)
+        self.n = aln.n_taxa
+
+    def key(self, edges):
+        return L.pt_topology_key(self.n, edges).tobytes()
+
+    def _optimize(self, edge_lists, brlen, masks=None, warm_rows=None):
+        """Optimises a batch; brlen is the concatenation of the trees' start
+        lengths.  warm_rows = (features, pos, base) applies the warm start on
+        the device first.  Returns (lnl, brlen, passes)."""
+        import torch
+        dev = torch.device("cuda", 0)
+        T = L.Trees(edge_lists)
+        mask = None if masks is None else np.concatenate(masks).astype(np.uint8)
+        plan = L.Plan(self.ctx, [self.aln], T, L.PT_PLAN_OPTIMIZE, self.precision, mask=mask)
+        stream = torch.cuda.current_stream(dev)
+        b = torch.tensor(brlen, dtype=torch.float64, device=dev)
+        if warm_rows is not None:
+            X, pos, base = warm_rows
+            self.warm.net.warm_start(torch.tensor(X, device=dev), torch.tensor(pos, device=dev),
+                                     torch.tensor(base, device=dev), b, self.opt.t_min, self.opt.t_max,
+                                     stream=stream)
+        nt = T.n_trees
+        lnl = torch.zeros(nt, dtype=torch.float64, device=dev)
+        ps = torch.zeros(nt, dtype=torch.int32, device=dev)
+        plan.optimize(b, lnl, ps, None, opt=self.opt, stream=stream)
+        torch.cuda.synchronize(dev)
+        out = lnl.cpu().numpy(), b.cpu().numpy(), ps.cpu().numpy()
+        plan.close()
+        return out
+
+    def run(self, starts, collect=False, max_samples=None):
+        """starts: list of (edges, brlen).  With collect, every proposal is
+        fully optimised and (features, log length ratios of the touched
+        edges) are recorded for training."""
+        n = self.n
+        E = 2 * n - 3
+        todo = []  # (key, edges, brlen)
+        queued = set()
+        for e, b in starts:
+            k = self.key(e)
+            if k not in queued:
+                queued.add(k)
+                todo.append((k, np.asarray(e, np.int32), np.asarray(b, np.float64)))
+        visited = set()
+        good = {}
+        lmax = -np.inf
+        stats = dict(proposed=0, queued=len(todo), full_passes=0, full_time=0.0, prop_time=0.0, batches=0)
+        samples = []
+        n_samples = 0
+        head = 0
+        while head < len(todo):
+            # ---- visit a batch: full optimisation
+            batch = []
+            while head < len(todo) and len(batch) < self.batch:
+                k, e, b = todo[head]
+                head += 1
+                if k in visited:
+                    continue
+                visited.add(k)
+                batch.append((k, e, b))
+            if not batch:
+                break
+            t0 = time.perf_counter()
+            lnl, bo, ps = self._optimize([e for _, e, _ in batch], np.concatenate([b for _, _, b in batch]))
+            stats["full_time"] += time.perf_counter() - t0
+            stats["full_passes"] += int(ps.sum())
+            stats["batches"] += 1
+            lmax = max(lmax, float(lnl.max()))
+            parents = []
+            for i, (k, e, _) in enumerate(batch):
+                if lnl[i] >= lmax + self.T:
+                    bi = bo[i * E:(i + 1) * E].copy()
+                    good[k] = (float(lnl[i]), e, bi)
+                    parents.append((e, bi))
+            # ---- propose the unvisited neighbours of the good ones
+            props = []  # (key, edges, start brlen, features row, touched, parent brlen)
+            for e, b in parents:
+                ne, nb, tt = L.pt_nni_neighbors(n, e, b)
+                F = L.pt_nni_features(n, e, b) if (self.warm is not None or collect) else None
+                for j in range(len(ne)):
+                    k = self.key(ne[j])
+                    if k in visited or k in queued:
+                        continue
+                    queued.add(k)
+                    props.append((k, ne[j], nb[j], None if F is None else F[j], tt[j], b))
+            stats["proposed"] += len(props)
+            radius = -1 if collect else self.radius
+            for s in range(0, len(props), self.batch):
+                if max_samples is not None and n_samples >= max_samples:
+                    break
+                chunk = props[s:s + self.batch]
+                masks = None
+                if radius == 0:
+                    masks = []
+                    for p in chunk:
+                        m = np.zeros(E, np.uint8)
+                        m[p[4][0]] = 1
+                        masks.append(m)
+                warm_rows = None
+                if self.warm is not None:
+                    X = np.stack([p[3] for p in chunk]).astype(np.float32)
+                    pos = np.stack([i * E + p[4] for i, p in enumerate(chunk)]).astype(np.int32)
+                    base = np.stack([p[5][p[4]] for p in chunk])
+                    warm_rows = (X, pos, base)
+                t0 = time.perf_counter()
+                lnl, bo, ps = self._optimize([p[1] for p in chunk], np.concatenate([p[2] for p in chunk]),
+                                             masks, warm_rows)
+                stats["prop_time"] += time.perf_counter() - t0
+                for i, p in enumerate(chunk):
+                    bi = bo[i * E:(i + 1) * E].copy()
+                    if collect:
+                        tt = p[4]
+                        y = np.log(np.maximum(bi[tt], 1e-6)) - np.log(np.maximum(p[5][tt], 1e-6))
+                        samples.append((p[3], y.astype(np.float32)))
+                        n_samples += 1
+                    if lnl[i] >= lmax + self.T:
+                        todo.append((p[0], p[1], bi))
+                        stats["queued"] += 1
+            if max_samples is not None and n_samples >= max_samples:
+                break
+        final = {k: v for k, v in good.items() if v[0] >= lmax + self.T}
+        return SearchResult(lmax=lmax, good=final, visited=len(visited), proposed=stats["proposed"],
+                            queued=stats["queued"], full_passes=stats["full_passes"],
+                            full_time_s=stats["full_time"], proposal_time_s=stats["prop_time"],
+                            batches=stats["batches"], samples=samples)
