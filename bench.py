@@ -35,9 +35,12 @@ def log(*a):
 
 
 def kernel_hash():
+    """Hash of the sources that decide the optimiser's work per launch (its
+    kernels and the host code that sets its programs and tolerances)."""
     h = hashlib.sha256()
-    with open(os.path.join(ROOT, "paper_1811_11007_amd", "csrc", "kernels.hip"), "rb") as f:
-        h.update(f.read())
+    for name in ("kernels.hip", "abi.cpp", "tree.cpp"):
+        with open(os.path.join(ROOT, "paper_1811_11007_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
     return h.hexdigest()[:16]
 
 

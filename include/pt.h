@@ -108,7 +108,11 @@ typedef struct {
     int32_t max_passes, max_newton;
 } pt_opt;
 
-/* Defaults for a precision (t_min 1e-8, t_max 100). */
+/* Defaults for a precision: t_min 1e-8, t_max 100, max_passes 200,
+ * max_newton 32; FP64 tol_lnl 1e-8, tol_t 1e-5, tol_newton 1e-9; FP32
+ * tol_lnl 1e-5, tol_t 1e-3, tol_newton 1e-6 (FP32 partials cannot resolve
+ * lnL changes much below 1e-5 on alignments of ~1e3 patterns; the reported
+ * lnL is evaluated from FP64 partials at the final lengths). */
 void pt_opt_default(int32_t precision, pt_opt *out);
 
 /* --------------------------------------------------- host-pointer batches */
@@ -275,12 +279,13 @@ pt_status pt_mlp_gradient(pt_mlp *mlp, const float *d_x, const float *d_target, 
                           double *d_loss, void *stream);
 /* Warm start of NNI neighbours: y = network(d_x) as above, then for every
  * row r and output o with d_pos[r][o] >= 0,
- *   d_brlen[d_pos[r][o]] = clamp(max(d_base[r][o], 1e-6) * exp(y[r][o]), t_min, t_max),
- * i.e. the outputs are log-ratios of a neighbour's lengths to its parent's.
- * d_pos: device int32[rows][n_out], indices into d_brlen (distinct, in
- * range: the caller's responsibility); d_base: device double[rows][n_out]. */
+ *   d_brlen[d_pos[r][o]] = clamp((max(d_base[r][o], 0) + shift) * exp(y[r][o]) - shift, t_min, t_max),
+ * i.e. the outputs are log-ratios of shifted lengths of a neighbour and its
+ * parent (shift > 0 keeps lengths near zero from dominating).  d_pos: device
+ * int32[rows][n_out], indices into d_brlen (distinct and in range: the
+ * caller's responsibility); d_base: device double[rows][n_out]. */
 pt_status pt_mlp_warm_start(pt_mlp *mlp, const float *d_x, int32_t rows, const int32_t *d_pos, const double *d_base,
-                            double t_min, double t_max, double *d_brlen, void *stream);
+                            double shift, double t_min, double t_max, double *d_brlen, void *stream);
 /* One Adam step on that loss. */
 pt_status pt_mlp_train_step(pt_mlp *mlp, const float *d_x, const float *d_target, int32_t rows,
                             const pt_adam *opt, double *d_loss, void *stream);

@@ -117,7 +117,8 @@ def lib():
         L.pt_mlp_get_params.argtypes = [vp, vp]
         L.pt_mlp_set_params.argtypes = [vp, vp]
         L.pt_mlp_forward.argtypes = [vp, vp, i32, vp, vp]
-        L.pt_mlp_warm_start.argtypes = [vp, vp, i32, vp, vp, ctypes.c_double, ctypes.c_double, vp, vp]
+        L.pt_mlp_warm_start.argtypes = [vp, vp, i32, vp, vp, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                        vp, vp]
         L.pt_mlp_gradient.argtypes = [vp, vp, vp, i32, vp, vp, vp]
         L.pt_mlp_train_step.argtypes = [vp, vp, vp, i32, P(pt_adam), vp, vp]
         for name in EXPORTS:
@@ -339,9 +340,10 @@ class MLP:
         check(lib().pt_mlp_forward(self.h, _dptr(d_x), int(d_x.shape[0]), _dptr(d_y), Plan._stream(stream)))
         return d_y
 
-    def warm_start(self, d_x, d_pos, d_base, d_brlen, t_min=1e-8, t_max=100.0, stream=None):
+    def warm_start(self, d_x, d_pos, d_base, d_brlen, t_min=1e-8, t_max=100.0, shift=1e-4, stream=None):
         check(lib().pt_mlp_warm_start(self.h, _dptr(d_x), int(d_x.shape[0]), _dptr(d_pos), _dptr(d_base),
-                                      float(t_min), float(t_max), _dptr(d_brlen), Plan._stream(stream)))
+                                      float(shift), float(t_min), float(t_max), _dptr(d_brlen),
+                                      Plan._stream(stream)))
 
     def gradient(self, d_x, d_t, d_grad, d_loss=None, stream=None):
         check(lib().pt_mlp_gradient(self.h, _dptr(d_x), _dptr(d_t), int(d_x.shape[0]), _dptr(d_grad),

@@ -1042,15 +1042,16 @@ pt_status pt_mlp_forward(pt_mlp *mlp, const float *d_x, int32_t rows, float *d_y
 }
 
 pt_status pt_mlp_warm_start(pt_mlp *mlp, const float *d_x, int32_t rows, const int32_t *d_pos, const double *d_base,
-                            double t_min, double t_max, double *d_brlen, void *stream) {
+                            double shift, double t_min, double t_max, double *d_brlen, void *stream) {
     if (!mlp || rows < 0 || (rows > 0 && (!d_x || !d_pos || !d_base || !d_brlen)))
         return fail(PT_EINVAL, "bad arguments");
     if (!(t_min > 0.0) || !(t_max > t_min)) return fail(PT_EINVAL, "need 0 < t_min < t_max");
+    if (!(shift > 0.0) || !std::isfinite(shift)) return fail(PT_EINVAL, "need shift > 0");
     pt_status st = mlp_scratch(mlp, rows);
     if (st) return st;
     hipStream_t s = (hipStream_t)stream;
     PT_HIP(pt::mlp_forward(d_x, mlp->d_p, rows, mlp->ni, mlp->nh, mlp->no, mlp->d_h, mlp->d_y, s));
-    PT_HIP(pt::mlp_warm_apply(mlp->d_y, d_pos, d_base, rows, mlp->no, t_min, t_max, d_brlen, s));
+    PT_HIP(pt::mlp_warm_apply(mlp->d_y, d_pos, d_base, rows, mlp->no, shift, t_min, t_max, d_brlen, s));
     return PT_OK;
 }
 

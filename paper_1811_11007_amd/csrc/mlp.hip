@@ -133,15 +133,16 @@ __global__ void k_sum_rows(const double *row_loss, int rows, double *out) {
     if (threadIdx.x == 0) *out = s;
 }
 
-// brlen[pos[r][o]] = clamp(max(base[r][o], 1e-6) * exp(y[r][o]), t_min, t_max)
-// for pos >= 0: the network predicts log-ratios of new to parent lengths.
-__global__ void k_warm_apply(const float *y, const int32_t *pos, const double *base, int rows, int no, double t_min,
-                             double t_max, double *brlen) {
+// brlen[pos[r][o]] = clamp((max(base[r][o], 0) + shift) * exp(y[r][o]) - shift,
+// t_min, t_max) for pos >= 0: the network predicts log-ratios of shifted new
+// and parent lengths.
+__global__ void k_warm_apply(const float *y, const int32_t *pos, const double *base, int rows, int no, double shift,
+                             double t_min, double t_max, double *brlen) {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= (int64_t)rows * no) return;
     const int32_t at = pos[g];
     if (at < 0) return;
-    const double v = fmax(base[g], 1e-6) * exp((double)y[g]);
+    const double v = (fmax(base[g], 0.0) + shift) * exp((double)y[g]) - shift;
     brlen[at] = fmin(fmax(v, t_min), t_max);
 }
 
@@ -175,11 +176,11 @@ hipError_t mlp_loss_grad(const float *y, const float *t, int rows, int no, float
     return hipGetLastError();
 }
 
-hipError_t mlp_warm_apply(const float *y, const int32_t *pos, const double *base, int rows, int no, double t_min,
-                          double t_max, double *brlen, hipStream_t s) {
+hipError_t mlp_warm_apply(const float *y, const int32_t *pos, const double *base, int rows, int no, double shift,
+                          double t_min, double t_max, double *brlen, hipStream_t s) {
     if (rows <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_warm_apply, dim3(blocks((int64_t)rows * no, 256)), dim3(256), 0, s, y, pos, base, rows, no,
-                       t_min, t_max, brlen);
+                       shift, t_min, t_max, brlen);
     return hipGetLastError();
 }
 

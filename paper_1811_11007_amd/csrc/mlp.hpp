@@ -15,9 +15,9 @@ hipError_t mlp_loss_grad(const float *y, const float *t, int rows, int no, float
 // grad (packed like the parameters) from dy, the inputs and the activations.
 hipError_t mlp_backward(const float *x, const float *p, const float *hact, const float *dy, int rows, int ni, int nh,
                         int no, float *dz, float *grad, hipStream_t s);
-// brlen[pos] = clamp(max(base, 1e-6) * exp(y), t_min, t_max) where pos >= 0.
-hipError_t mlp_warm_apply(const float *y, const int32_t *pos, const double *base, int rows, int no, double t_min,
-                          double t_max, double *brlen, hipStream_t s);
+// brlen[pos] = clamp((max(base, 0) + shift) * exp(y) - shift, t_min, t_max) where pos >= 0.
+hipError_t mlp_warm_apply(const float *y, const int32_t *pos, const double *base, int rows, int no, double shift,
+                          double t_min, double t_max, double *brlen, hipStream_t s);
 // Adam step with bias corrections c1 = 1 - b1^t, c2 = 1 - b2^t.
 hipError_t mlp_adam(float *p, const float *g, float *m, float *v, int n, float lr, float b1, float b2, float eps,
                     float c1, float c2, hipStream_t s);

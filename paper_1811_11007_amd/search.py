@@ -45,20 +45,27 @@ class SearchResult:
     full_time_s: float
     proposal_time_s: float
     batches: int
-    samples: list = field(default_factory=list)  # (features, targets) arrays, when collecting
+    warm_better: int = 0  # proposals whose warm-started partial optimum beat the cold-started one
+    samples: list = field(default_factory=list)  # (features, parent lengths, optimised lengths) of the
+                                                 # five touched edges, when collecting
 
 
 class WarmStart:
-    """A trained network that predicts the five touched lengths of a move."""
+    """A trained network that predicts the five touched lengths of a move as
+    t = (t_parent + shift) * exp(y) - shift."""
 
-    def __init__(self, ctx, params, n_hidden=128):
+    def __init__(self, ctx, params, n_hidden=128, shift=1e-4):
         self.net = L.MLP(ctx, L.PT_NNI_FEATURES, n_hidden, 5, params)
+        self.shift = float(shift)
 
     @classmethod
     def load(cls, ctx, path):
         import json
         d = json.load(open(path))
-        return cls(ctx, np.asarray(d["params"], np.float32), d["n_hidden"])
+        return cls(ctx, np.asarray(d["params"], np.float32), d["n_hidden"], d.get("shift", 1e-4))
+
+    def apply(self, d_x, d_pos, d_base, d_brlen, t_min=1e-8, t_max=100.0, stream=None):
+        self.net.warm_start(d_x, d_pos, d_base, d_brlen, t_min, t_max, self.shift, stream=stream)
 
 
 class ThresholdSearch:
@@ -89,9 +96,8 @@ class ThresholdSearch:
         b = torch.tensor(brlen, dtype=torch.float64, device=dev)
         if warm_rows is not None:
             X, pos, base = warm_rows
-            self.warm.net.warm_start(torch.tensor(X, device=dev), torch.tensor(pos, device=dev),
-                                     torch.tensor(base, device=dev), b, self.opt.t_min, self.opt.t_max,
-                                     stream=stream)
+            self.warm.apply(torch.tensor(X, device=dev), torch.tensor(pos, device=dev),
+                            torch.tensor(base, device=dev), b, self.opt.t_min, self.opt.t_max, stream=stream)
         nt = T.n_trees
         lnl = torch.zeros(nt, dtype=torch.float64, device=dev)
         ps = torch.zeros(nt, dtype=torch.int32, device=dev)
@@ -101,10 +107,11 @@ class ThresholdSearch:
         plan.close()
         return out
 
-    def run(self, starts, collect=False, max_samples=None):
+    def run(self, starts, collect=False, max_samples=None, progress=None):
         """starts: list of (edges, brlen).  With collect, every proposal is
-        fully optimised and (features, log length ratios of the touched
-        edges) are recorded for training."""
+        fully optimised and (features, parent and optimised lengths of the
+        five touched edges) are recorded for training.  progress, if given,
+        is called with a one-line summary after every batch of visits."""
         n = self.n
         E = 2 * n - 3
         todo = []  # (key, edges, brlen)
@@ -117,7 +124,8 @@ class ThresholdSearch:
         visited = set()
         good = {}
         lmax = -np.inf
-        stats = dict(proposed=0, queued=len(todo), full_passes=0, full_time=0.0, prop_time=0.0, batches=0)
+        stats = dict(proposed=0, queued=len(todo), full_passes=0, full_time=0.0, prop_time=0.0, batches=0,
+                     warm_better=0)
         samples = []
         n_samples = 0
         head = 0
@@ -157,11 +165,22 @@ class ThresholdSearch:
                     queued.add(k)
                     props.append((k, ne[j], nb[j], None if F is None else F[j], tt[j], b))
             stats["proposed"] += len(props)
+            if progress is not None:
+                progress("batch %d: %d visited, %d good, %d new proposals, lmax %.4f" % (
+                    stats["batches"], len(visited), len(good), len(props), lmax))
             radius = -1 if collect else self.radius
-            for s in range(0, len(props), self.batch):
+            # with a warm start every proposal is optimised from both starts in
+            # the same launch and keeps the better result: the cold start stays
+            # the fallback, so the gate is never looser than without the network
+            dual = self.warm is not None
+            step = max(1, self.batch // 2) if dual else self.batch
+            for s in range(0, len(props), step):
                 if max_samples is not None and n_samples >= max_samples:
                     break
-                chunk = props[s:s + self.batch]
+                chunk = props[s:s + step]
+                nc = len(chunk)
+                trees = [p[1] for p in chunk]
+                starts = np.concatenate([p[2] for p in chunk])
                 masks = None
                 if radius == 0:
                     masks = []
@@ -170,23 +189,29 @@ class ThresholdSearch:
                         m[p[4][0]] = 1
                         masks.append(m)
                 warm_rows = None
-                if self.warm is not None:
+                if dual:
                     X = np.stack([p[3] for p in chunk]).astype(np.float32)
-                    pos = np.stack([i * E + p[4] for i, p in enumerate(chunk)]).astype(np.int32)
+                    pos = np.stack([(nc + i) * E + p[4] for i, p in enumerate(chunk)]).astype(np.int32)
                     base = np.stack([p[5][p[4]] for p in chunk])
                     warm_rows = (X, pos, base)
+                    trees = trees + trees
+                    starts = np.concatenate([starts, starts])
+                    masks = None if masks is None else masks + masks
                 t0 = time.perf_counter()
-                lnl, bo, ps = self._optimize([p[1] for p in chunk], np.concatenate([p[2] for p in chunk]),
-                                             masks, warm_rows)
+                lnl, bo, ps = self._optimize(trees, starts, masks, warm_rows)
                 stats["prop_time"] += time.perf_counter() - t0
                 for i, p in enumerate(chunk):
-                    bi = bo[i * E:(i + 1) * E].copy()
+                    j = i
+                    if dual and lnl[nc + i] > lnl[i]:
+                        j = nc + i
+                        stats["warm_better"] += 1
+                    li = lnl[j]
+                    bi = bo[j * E:(j + 1) * E].copy()
                     if collect:
                         tt = p[4]
-                        y = np.log(np.maximum(bi[tt], 1e-6)) - np.log(np.maximum(p[5][tt], 1e-6))
-                        samples.append((p[3], y.astype(np.float32)))
+                        samples.append((p[3], p[5][tt].copy(), bi[tt].copy()))
                         n_samples += 1
-                    if lnl[i] >= lmax + self.T:
+                    if li >= lmax + self.T:
                         todo.append((p[0], p[1], bi))
                         stats["queued"] += 1
             if max_samples is not None and n_samples >= max_samples:
@@ -195,4 +220,4 @@ class ThresholdSearch:
         return SearchResult(lmax=lmax, good=final, visited=len(visited), proposed=stats["proposed"],
                             queued=stats["queued"], full_passes=stats["full_passes"],
                             full_time_s=stats["full_time"], proposal_time_s=stats["prop_time"],
-                            batches=stats["batches"], samples=samples)
+                            batches=stats["batches"], warm_better=stats["warm_better"], samples=samples)

@@ -8,7 +8,9 @@
 2. Fully optimises the generating topology (the start tree) and runs the
    threshold search from it with every proposal fully optimised, recording
    for each proposed neighbour the features of its move in the parent and
-   the log-ratios of its five optimised touched lengths to the parent's.
+   its five optimised touched lengths beside the parent's.  The targets are
+   log((t_new + s) / (t_parent + s)) with s = 1e-4, so lengths at or near
+   the lower bound do not dominate the loss.
    The collection threshold widens until the sample target is reached.
 3. Trains the 14 -> 128 (tanh) -> 5 perceptron on the GPU with the
    library's own forward, backward and Adam kernels (minibatches, mean
@@ -119,6 +121,8 @@ def main():
     ap.add_argument("--seed", type=int, default=5)
     ap.add_argument("--samples", type=int, default=100000)
     ap.add_argument("--epochs", type=int, default=40)
+    ap.add_argument("--shift", type=float, default=1e-4)
+    ap.add_argument("--save-data", default=None, help="also write the collected samples (.npz)")
     args = ap.parse_args()
     import torch  # noqa: F401
     from . import _lib as L
@@ -134,7 +138,7 @@ def main():
     for T in (-10.0, -30.0, -100.0, -300.0, -1000.0):
         t0 = time.perf_counter()
         res = ThresholdSearch(ctx, A, threshold=T, batch=1024).run(
-            [(e, b0)], collect=True, max_samples=args.samples)
+            [(e, b0)], collect=True, max_samples=args.samples, progress=log)
         samples = res.samples
         colls.append({"threshold": T, "samples": len(samples), "good": len(res.good), "visited": res.visited,
                       "seconds": round(time.perf_counter() - t0, 2)})
@@ -142,9 +146,13 @@ def main():
         if len(samples) >= args.samples:
             break
     X = np.stack([s[0] for s in samples]).astype(np.float64)
-    Y = np.stack([s[1] for s in samples]).astype(np.float32)
+    Tp = np.stack([s[1] for s in samples])
+    Tn = np.stack([s[2] for s in samples])
+    if args.save_data:
+        np.savez_compressed(args.save_data, X=X.astype(np.float32), t_parent=Tp, t_new=Tn)
+    Y = (np.log(Tn + args.shift) - np.log(np.maximum(Tp, 0.0) + args.shift)).astype(np.float32)
     params, rec = train(ctx, X, Y, epochs=args.epochs)
-    out = {"n_in": L.PT_NNI_FEATURES, "n_hidden": 128, "n_out": 5,
+    out = {"n_in": L.PT_NNI_FEATURES, "n_hidden": 128, "n_out": 5, "shift": args.shift,
            "workload": "64 taxa x 2500 sites GTR+G4 (seed %d, %d patterns)" % (args.seed, aln.n_patterns),
            "collection": colls, "samples": len(samples), "training": rec,
            "params": [float(x) for x in params]}

@@ -122,16 +122,19 @@ def test_warm_start_scatter_against_oracle(ctx):
     pos = rng.permutation(n_len)[: rows * NO].reshape(rows, NO).astype(np.int32)
     pos[3, 2] = -1  # skipped
     base = rng.exponential(0.05, (rows, NO))
-    base[5, 1] = 0.0  # floored at 1e-6
+    base[5, 1] = 0.0
+    base[6, 2] = -1.0  # negative lengths count as 0
+    shift = 1e-4
     B = dev(brlen)
-    net.warm_start(dev(x), dev(pos), dev(base), B, t_min=1e-8, t_max=100.0)
+    net.warm_start(dev(x), dev(pos), dev(base), B, t_min=1e-8, t_max=100.0, shift=shift)
     got = B.cpu().numpy()
     _, y = om.forward(x.astype(np.float64), p.astype(np.float64), NI, NH, NO)
     want = brlen.copy()
     for r in range(rows):
         for o in range(NO):
             if pos[r, o] >= 0:
-                want[pos[r, o]] = min(max(max(base[r, o], 1e-6) * np.exp(y[r, o]), 1e-8), 100.0)
+                v = (max(base[r, o], 0.0) + shift) * np.exp(y[r, o]) - shift
+                want[pos[r, o]] = min(max(v, 1e-8), 100.0)
     assert np.max(np.abs(got - want) / want) <= 2e-4
     net.close()
 
@@ -147,3 +150,124 @@ def test_mlp_errors(ctx):
     with pytest.raises(ValueError):
         net.set_params(np.zeros(3))
     net.close()
+
+
+WEIGHTS = __import__("os").path.join(__import__("os").path.dirname(pt.__file__), "warmstart_64x2500.json")
+
+
+def test_warm_start_gain_on_held_out_alignment(ctx):
+    """The trained network (fit on the seed-5 alignment) on a held-out
+    64 x 2500 GTR+G4 alignment (seed 6): all 122 NNI neighbours of the
+    optimised generating tree.
+
+    Gains over the cold start (lengths inherited from the parent):
+      - its starting lengths for the five touched edges are closer to the
+        neighbours' optima (log(t + 1e-4) squared error, the centre edge by
+        far the most);
+      - radius-0 proposals (only the new edge optimised, the gate of the
+        search) started from the better of the two starts reach partial
+        likelihoods closer to the full optima.
+    The full optima are the same from either start: the network moves only
+    the starting point (the cold-start optimum is the judge)."""
+    import torch
+    from paper_1811_11007_amd.search import WarmStart
+    from paper_1811_11007_amd.train_warmstart import optimise_start, workload
+    say("warm start gain: held-out seed 6")
+    e, b, aln = workload(6)
+    n = 64
+    A = pt.Alignment.from_synth(ctx, aln)
+    b0, _ = optimise_start(ctx, A, e, b)
+    ne, nb, tt = pt.pt_nni_neighbors(n, e, b0)
+    F = pt.pt_nni_features(n, e, b0)
+    warm = WarmStart.load(ctx, WEIGHTS)
+    E = 2 * n - 3
+    K = len(ne)
+    T = pt.Trees(list(ne))
+    pos = (np.arange(K)[:, None] * E + tt).astype(np.int32)
+    base = b0[tt]
+
+    def start(use_warm):
+        B = dev(nb.ravel().copy())
+        if use_warm:
+            warm.apply(dev(F), dev(pos), dev(base), B)
+        return B
+
+    def run(B, mask=None):
+        plan = pt.Plan(ctx, [A], T, pt.PT_PLAN_OPTIMIZE, pt.PT_FP32, mask=mask)
+        lnl = torch.zeros(K, dtype=torch.float64, device="cuda:0")
+        ps = torch.zeros(K, dtype=torch.int32, device="cuda:0")
+        plan.optimize(B, lnl, ps)
+        torch.cuda.synchronize()
+        out = lnl.cpu().numpy(), ps.cpu().numpy(), B.cpu().numpy()
+        plan.close()
+        return out
+
+    bw0 = start(True).cpu().numpy()
+    lc, pc, bc = run(start(False))
+    lw, pw, bw = run(start(True))
+    s = 1e-4
+    err_c = (np.log(nb.ravel()[pos] + s) - np.log(bc[pos] + s)) ** 2
+    err_w = (np.log(bw0[pos] + s) - np.log(bc[pos] + s)) ** 2
+    say("touched-length error cold", err_c.mean(axis=0).round(3), "warm", err_w.mean(axis=0).round(3))
+    say("passes cold %d warm %d; max |dlnL| %.2e" % (pc.sum(), pw.sum(), np.max(np.abs(lw - lc))))
+    assert err_w[:, 0].mean() < 0.5 * err_c[:, 0].mean()
+    assert err_w[:, 1:].mean() < err_c[:, 1:].mean()
+    close = np.abs(lw - lc) <= 1e-3
+    assert close.mean() >= 0.97, np.sort(np.abs(lw - lc))[-5:]
+    mask = np.zeros((K, E), np.uint8)
+    mask[np.arange(K), tt[:, 0]] = 1
+    l0c, _, _ = run(start(False), mask.ravel())
+    l0w, _, _ = run(start(True), mask.ravel())
+    l0 = np.maximum(l0c, l0w)
+    full = np.maximum(lc, lw)
+    gap_c, gap_d = np.mean(full - l0c), np.mean(full - l0)
+    say("radius-0 gap to the full optimum: cold %.3f, better of both starts %.3f (warm better for %d of %d)" % (
+        gap_c, gap_d, int((l0w > l0c).sum()), K))
+    assert gap_d < 0.9 * gap_c
+
+
+def key_int(k, n):
+    W = (n + 63) // 64
+    return [str(sum(int(row[w]) << (64 * w) for w in range(W))) for row in k]
+
+
+def test_warm_started_optima_match_oracle(ctx):
+    """The cold-start oracle judges the warm start's results.  The oracle
+    optimised the held-out generating tree from its simulated lengths and
+    four NNI neighbours from the lengths they inherit (stored by
+    tests/golden/make_warm64.py); the GPU's optimum of the start tree and
+    its warm-started optima of those neighbours must agree with them to the
+    FP32 bar."""
+    import json
+    import os
+    import torch
+    from paper_1811_11007_amd.search import WarmStart
+    from paper_1811_11007_amd.train_warmstart import optimise_start, workload
+    say("warm start vs oracle: held-out seed 6")
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "warm64_heldout.json")))
+    e, b, aln = workload(g["seed"])
+    n = g["n_taxa"]
+    assert aln.n_patterns == g["n_patterns"]
+    A = pt.Alignment.from_synth(ctx, aln)
+    b0, l0 = optimise_start(ctx, A, e, b)
+    assert key_int(pt.pt_topology_key(n, e), n) == g["start"]["key"]
+    say("start: oracle %.6f gpu %.6f" % (g["start"]["lnl"], l0))
+    assert abs(l0 - g["start"]["lnl"]) <= 1e-4
+    ne, nb, tt = pt.pt_nni_neighbors(n, e, b0)
+    F = pt.pt_nni_features(n, e, b0)
+    warm = WarmStart.load(ctx, WEIGHTS)
+    idx = [x["index"] for x in g["neighbours"]]
+    for i, x in zip(idx, g["neighbours"]):
+        assert key_int(pt.pt_topology_key(n, ne[i]), n) == x["key"]
+    plan = pt.Plan(ctx, [A], pt.Trees([ne[i] for i in idx]), pt.PT_PLAN_OPTIMIZE, pt.PT_FP32)
+    E = 2 * n - 3
+    B = dev(np.concatenate([nb[i] for i in idx]))
+    pos = (np.arange(len(idx))[:, None] * E + tt[idx]).astype(np.int32)
+    warm.apply(dev(F[idx]), dev(pos), dev(b0[tt[idx]]), B)
+    lnl = torch.zeros(len(idx), dtype=torch.float64, device="cuda:0")
+    plan.optimize(B, lnl)
+    got = lnl.cpu().numpy()
+    want = np.array([x["lnl"] for x in g["neighbours"]])
+    say("neighbours: max |gpu warm - oracle| %.2e" % np.max(np.abs(got - want)))
+    assert np.max(np.abs(got - want)) <= 1e-4
+    plan.close()
