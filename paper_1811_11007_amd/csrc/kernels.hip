@@ -37,6 +37,12 @@ struct Store;
 template <>
 struct Store<float> {
     static constexpr int kScaleExp = 64;
+    // one category's four states as loaded, widened when used
+    using Raw = float4;
+    __device__ static inline Raw load_raw(const float *p) { return *reinterpret_cast<const float4 *>(p); }
+    __device__ static inline void widen(const Raw &v, double x[4]) {
+        x[0] = v.x; x[1] = v.y; x[2] = v.z; x[3] = v.w;
+    }
     __device__ static inline void load(const float *p, double x[4]) {
         float4 v = *reinterpret_cast<const float4 *>(p);
         x[0] = v.x; x[1] = v.y; x[2] = v.z; x[3] = v.w;
@@ -50,6 +56,18 @@ struct Store<float> {
 template <>
 struct Store<double> {
     static constexpr int kScaleExp = 256;
+    struct Raw {
+        double2 a, b;
+    };
+    __device__ static inline Raw load_raw(const double *p) {
+        Raw r;
+        r.a = reinterpret_cast<const double2 *>(p)[0];
+        r.b = reinterpret_cast<const double2 *>(p)[1];
+        return r;
+    }
+    __device__ static inline void widen(const Raw &v, double x[4]) {
+        x[0] = v.a.x; x[1] = v.a.y; x[2] = v.b.x; x[3] = v.b.y;
+    }
     __device__ static inline void load(const double *p, double x[4]) {
         double2 a = reinterpret_cast<const double2 *>(p)[0];
         double2 b = reinterpret_cast<const double2 *>(p)[1];
@@ -191,11 +209,38 @@ __device__ inline void wave_expo(double *wx, const ModelS *md, int K, double t) 
     __builtin_amdgcn_wave_barrier();
 }
 
-// OP_UPDATE for this thread's patterns:
+// One side of an update or edge evaluation for one pattern: a tip code, or
+// the scaler count and every category's partial of a slot.  TIP is a
+// template parameter so that the code fetching a pattern's sides has no
+// branch between its loads: they are all issued before the first is used,
+// and their memory round trips overlap.
+template <typename T, int KP, bool TIP>
+struct Side {
+    typename Store<T>::Raw r[KP];
+    unsigned code;
+    int c;
+    __device__ inline void fetch(const TreeView<T> &v, int ref, int p) {
+        if constexpr (TIP) {
+            code = ldg(v.tips + (size_t)(-ref - 1) * v.P + p);
+            c = 0;
+        } else {
+            c = v.cnt[(size_t)ref * v.P + p];
+            // the layout holds KP categories, so padded ones are in bounds
+#pragma unroll
+            for (int k = 0; k < KP; ++k) r[k] = Store<T>::load_raw(slot_ptr<T, KP>(v, ref, k, p));
+        }
+    }
+    __device__ inline void get(int k, double x[4]) const {
+        if constexpr (TIP) tip_vec(code, x);
+        else Store<T>::widen(r[k], x);
+    }
+};
+
+// OP_UPDATE for this thread's patterns, sides of kinds TA / TB (tip or slot):
 //   dst[k] = (P_k(t_ea) . side a[k]) * (P_k(t_eb) . side b[k]), elementwise over
 // states, for every category k, then per-pattern scaling.
-template <typename T, int BS, int KP>
-__device__ inline void do_update(const TreeView<T> &v, const Op &op, int base, int ni) {
+template <typename T, int BS, int KP, bool TA, bool TB>
+__device__ inline void update_sides(const TreeView<T> &v, const Op &op, int base, int ni) {
     const double *pm = v.pm;
     const double thr = ldexp(1.0, -Store<T>::kScaleExp);
     const double up = ldexp(1.0, Store<T>::kScaleExp);
@@ -203,39 +248,31 @@ __device__ inline void do_update(const TreeView<T> &v, const Op &op, int base, i
     for (int j = 0; j < ni; ++j) {
         const int p = base + j * BS + threadIdx.x;
         if (p >= v.P) break;
-        int c = 0;
-        unsigned ta = 0, tb = 0;
-        if (op.a < 0) ta = ldg(v.tips + (size_t)(-op.a - 1) * v.P + p);
-        else c += v.cnt[(size_t)op.a * v.P + p];
-        if (op.b < 0) tb = ldg(v.tips + (size_t)(-op.b - 1) * v.P + p);
-        else c += v.cnt[(size_t)op.b * v.P + p];
-        // All categories' loads are issued before any arithmetic; the layout
-        // holds KP categories, so padded ones are in bounds and ignored.
-        double xa[KP][4], xb[KP][4];
-#pragma unroll
-        for (int k = 0; k < KP; ++k) {
-            if (op.a < 0) tip_vec(ta, xa[k]);
-            else Store<T>::load(slot_ptr<T, KP>(v, op.a, k, p), xa[k]);
-            if (op.b < 0) tip_vec(tb, xb[k]);
-            else Store<T>::load(slot_ptr<T, KP>(v, op.b, k, p), xb[k]);
-        }
+        Side<T, KP, TA> sa;
+        Side<T, KP, TB> sb;
+        sa.fetch(v, op.a, p);
+        sb.fetch(v, op.b, p);
         double o[KP][4];
         double mx = 0.0;
 #pragma unroll
         for (int k = 0; k < KP; ++k) {
+            double xa[4], xb[4];
+            sa.get(k, xa);
+            sb.get(k, xb);
             const double *Pa = pm + ((size_t)op.ea * KP + k) * 16;
             const double *Pb = pm + ((size_t)op.eb * KP + k) * 16;
             const bool live = k < v.K;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const double sa = Pa[i * 4] * xa[k][0] + Pa[i * 4 + 1] * xa[k][1] + Pa[i * 4 + 2] * xa[k][2] +
-                                  Pa[i * 4 + 3] * xa[k][3];
-                const double sb = Pb[i * 4] * xb[k][0] + Pb[i * 4 + 1] * xb[k][1] + Pb[i * 4 + 2] * xb[k][2] +
-                                  Pb[i * 4 + 3] * xb[k][3];
-                o[k][i] = live ? sa * sb : 0.0;
+                const double xsa = Pa[i * 4] * xa[0] + Pa[i * 4 + 1] * xa[1] + Pa[i * 4 + 2] * xa[2] +
+                                   Pa[i * 4 + 3] * xa[3];
+                const double xsb = Pb[i * 4] * xb[0] + Pb[i * 4 + 1] * xb[1] + Pb[i * 4 + 2] * xb[2] +
+                                   Pb[i * 4 + 3] * xb[3];
+                o[k][i] = live ? xsa * xsb : 0.0;
                 mx = fmax(mx, o[k][i]);
             }
         }
+        int c = sa.c + sb.c;
         if (mx < thr && mx > 0.0) {
 #pragma unroll
             for (int k = 0; k < KP; ++k)
@@ -250,40 +287,16 @@ __device__ inline void do_update(const TreeView<T> &v, const Op &op, int base, i
     }
 }
 
-// Eigenbasis coefficients of pattern p, category k, across an edge with
-// sides a and b:  s_m = (sum_i pi_i A_i U_im)(sum_j Uinv_mj B_j)
-// = (sum_i W_im A_i)(sum_j W_jm B_j), so L_k(t) = sum_m s_m exp(lam_m r_k t).
-template <typename T, int KP>
-__device__ inline void coeffs(const TreeView<T> &v, const ModelS *md, int a, int b, unsigned ta, unsigned tb,
-                              int k, int p, double s[4]) {
-    double xa[4], xb[4];
-    if (a < 0) tip_vec(ta, xa);
-    else Store<T>::load(slot_ptr<T, KP>(v, a, k, p), xa);
-    if (b < 0) tip_vec(tb, xb);
-    else Store<T>::load(slot_ptr<T, KP>(v, b, k, p), xb);
-#pragma unroll
-    for (int m = 0; m < 4; ++m) {
-        double ua = 0.0, vb = 0.0;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const double wim = md->W[i * 4 + m];
-            ua += wim * xa[i];
-            vb += wim * xb[i];
-        }
-        s[m] = ua * vb;
+// OP_UPDATE for this thread's patterns base + j*BS, j < ni.
+template <typename T, int BS, int KP>
+__device__ inline void do_update(const TreeView<T> &v, const Op &op, int base, int ni) {
+    if (op.a < 0) {
+        if (op.b < 0) update_sides<T, BS, KP, true, true>(v, op, base, ni);
+        else update_sides<T, BS, KP, true, false>(v, op, base, ni);
+    } else {
+        if (op.b < 0) update_sides<T, BS, KP, false, true>(v, op, base, ni);
+        else update_sides<T, BS, KP, false, false>(v, op, base, ni);
     }
-}
-
-// Tip codes of the two sides (0 for partials) and the pattern's scaler total.
-template <typename T>
-__device__ inline int side_codes(const TreeView<T> &v, int a, int b, int p, unsigned &ta, unsigned &tb) {
-    int c = 0;
-    ta = tb = 0;
-    if (a < 0) ta = ldg(v.tips + (size_t)(-a - 1) * v.P + p);
-    else c += v.cnt[(size_t)a * v.P + p];
-    if (b < 0) tb = ldg(v.tips + (size_t)(-b - 1) * v.P + p);
-    else c += v.cnt[(size_t)b * v.P + p];
-    return c;
 }
 
 // t-independent part of a pattern's lnL: scaler corrections and the 1/K
@@ -298,43 +311,75 @@ struct Sums3 {
     int parity;
 };
 
+// Eigenbasis coefficients from the two sides' state vectors of one category.
+__device__ inline void coeffs_x(const ModelS *md, const double xa[4], const double xb[4], double s[4]) {
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        double ua = 0.0, vb = 0.0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const double wim = md->W[i * 4 + m];
+            ua += wim * xa[i];
+            vb += wim * xb[i];
+        }
+        s[m] = ua * vb;
+    }
+}
+
+// This thread's contributions to lnL, d1 and d2 across an edge whose sides
+// are of kinds TA / TB, with the exponentials of its length in wx.
+template <typename T, int BS, int KP, bool TA, bool TB>
+__device__ inline void eval_sides(const TreeView<T> &v, int a, int b, int base, int ni, const double *wx,
+                                  double logK, Sums3 &r) {
+    const ModelS *md = v.m;
+#pragma unroll 1
+    for (int j = 0; j < ni; ++j) {
+        const int p = base + j * BS + threadIdx.x;
+        if (p >= v.P) break;
+        Side<T, KP, TA> sa;
+        Side<T, KP, TB> sb;
+        sa.fetch(v, a, p);
+        sb.fetch(v, b, p);
+        const double w = ldg(v.w + p);
+        double L = 0.0, L1 = 0.0, L2 = 0.0;
+#pragma unroll
+        for (int k = 0; k < KP; ++k) {
+            if (k < v.K) {
+                double xa[4], xb[4], sk[4];
+                sa.get(k, xa);
+                sb.get(k, xb);
+                coeffs_x(md, xa, xb, sk);
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    L += sk[m] * wx[k * 4 + m];
+                    L1 += sk[m] * wx[4 * kMaxCats + k * 4 + m];
+                    L2 += sk[m] * wx[8 * kMaxCats + k * 4 + m];
+                }
+            }
+        }
+        const double inv = recip(L);
+        const double r1 = L1 * inv;
+        r.l0 += w * (log(L) + const_term<T>(sa.c + sb.c, logK));
+        r.l1 += w * r1;
+        r.l2 += w * (L2 * inv - r1 * r1);
+    }
+}
+
 // OP_EVAL: block totals of lnL and its first two derivatives across an edge
 // at length t, computed on the fly from the two sides.
 template <typename T, int BS, int KP>
 __device__ inline Sums3 eval_edge(const TreeView<T> &v, int a, int b, int base, int ni, double t, double *red,
                                   double *wx, int parity) {
-    const ModelS *md = v.m;
-    wave_expo(wx, md, v.K, t);
+    wave_expo(wx, v.m, v.K, t);
     const double logK = log((double)v.K);
     Sums3 r;
     r.l0 = r.l1 = r.l2 = 0.0;
-#pragma unroll 1
-    for (int j = 0; j < ni; ++j) {
-        const int p = base + j * BS + threadIdx.x;
-        if (p >= v.P) break;
-        unsigned ta, tb;
-        const int c = side_codes(v, a, b, p, ta, tb);
-        double s[KP][4];
-#pragma unroll
-        for (int k = 0; k < KP; ++k) coeffs<T, KP>(v, md, a, b, ta, tb, k, p, s[k]);
-        double L = 0.0, L1 = 0.0, L2 = 0.0;
-#pragma unroll
-        for (int k = 0; k < KP; ++k) {
-            if (k < v.K) {
-#pragma unroll
-                for (int m = 0; m < 4; ++m) {
-                    L += s[k][m] * wx[k * 4 + m];
-                    L1 += s[k][m] * wx[4 * kMaxCats + k * 4 + m];
-                    L2 += s[k][m] * wx[8 * kMaxCats + k * 4 + m];
-                }
-            }
-        }
-        const double w = ldg(v.w + p);
-        const double inv = recip(L);
-        const double r1 = L1 * inv;
-        r.l0 += w * (log(L) + const_term<T>(c, logK));
-        r.l1 += w * r1;
-        r.l2 += w * (L2 * inv - r1 * r1);
+    if (a < 0) {
+        if (b < 0) eval_sides<T, BS, KP, true, true>(v, a, b, base, ni, wx, logK, r);
+        else eval_sides<T, BS, KP, true, false>(v, a, b, base, ni, wx, logK, r);
+    } else {
+        if (b < 0) eval_sides<T, BS, KP, false, true>(v, a, b, base, ni, wx, logK, r);
+        else eval_sides<T, BS, KP, false, false>(v, a, b, base, ni, wx, logK, r);
     }
     block_sum3<BS>(r.l0, r.l1, r.l2, red, parity);
     r.parity = parity;
@@ -346,6 +391,39 @@ struct EdgeResult {
     int parity, iters;
     long long cyc_table, cyc_iters;
 };
+
+// The eigenbasis table of an edge whose sides are of kinds TA / TB: this
+// thread's rows of tab ([k][row][4]) and wrow; returns the sum of its rows'
+// t-independent lnL terms.
+template <typename T, int BS, int KP, bool TA, bool TB>
+__device__ inline double table_sides(const TreeView<T> &v, int a, int b, int ni, size_t rows, T *tab, double *wrow,
+                                     double logK) {
+    const ModelS *md = v.m;
+    double cterm = 0.0;
+#pragma unroll 1
+    for (int j = 0; j < ni; ++j) {
+        const int p = j * BS + threadIdx.x;
+        if (p >= v.P) break;
+        Side<T, KP, TA> sa;
+        Side<T, KP, TB> sb;
+        sa.fetch(v, a, p);
+        sb.fetch(v, b, p);
+        const double w = ldg(v.w + p);
+        cterm += w * const_term<T>(sa.c + sb.c, logK);
+        wrow[j * BS + threadIdx.x] = w;
+#pragma unroll
+        for (int k = 0; k < KP; ++k) {
+            if (k < v.K) {
+                double xa[4], xb[4], sk[4];
+                sa.get(k, xa);
+                sb.get(k, xb);
+                coeffs_x(md, xa, xb, sk);
+                Store<T>::store(tab + ((size_t)k * rows + j * BS + threadIdx.x) * 4, sk);
+            }
+        }
+    }
+    return cterm;
+}
 
 // OP_NEWTON: safeguarded, projected Newton on the length of one edge.
 //  - the eigenbasis coefficients of this thread's patterns are computed once
@@ -370,22 +448,13 @@ __device__ inline EdgeResult newton_edge(const TreeView<T> &v, int a, int b, dou
     const size_t rows = (size_t)BS * ni;
     const double logK = log((double)v.K);
     const long long c0 = clock64();
-    double cterm = 0.0;
-#pragma unroll 1
-    for (int j = 0; j < ni; ++j) {
-        const int p = j * BS + threadIdx.x;
-        if (p >= v.P) break;
-        unsigned ta, tb;
-        const int c = side_codes(v, a, b, p, ta, tb);
-        const double w = ldg(v.w + p);
-        cterm += w * const_term<T>(c, logK);
-        wrow[j * BS + threadIdx.x] = w;
-        double s[KP][4];
-#pragma unroll
-        for (int k = 0; k < KP; ++k) coeffs<T, KP>(v, md, a, b, ta, tb, k, p, s[k]);
-#pragma unroll
-        for (int k = 0; k < KP; ++k)
-            if (k < v.K) Store<T>::store(tab + ((size_t)k * rows + j * BS + threadIdx.x) * 4, s[k]);
+    double cterm;
+    if (a < 0) {
+        if (b < 0) cterm = table_sides<T, BS, KP, true, true>(v, a, b, ni, rows, tab, wrow, logK);
+        else cterm = table_sides<T, BS, KP, true, false>(v, a, b, ni, rows, tab, wrow, logK);
+    } else {
+        if (b < 0) cterm = table_sides<T, BS, KP, false, true>(v, a, b, ni, rows, tab, wrow, logK);
+        else cterm = table_sides<T, BS, KP, false, false>(v, a, b, ni, rows, tab, wrow, logK);
     }
     const long long c1 = clock64();
     double lo = opt.t_min, hi = opt.t_max;
@@ -520,8 +589,21 @@ __global__ void __launch_bounds__(BS) k_tiles(const BatchArgs a, const double *b
     const int tile = blockIdx.x;
     const TreeDev td = a.trees[a.tile_tree[tile]];
     const AlnDev *aln = a.alns + td.aln;
-    const int n_pm = td.n_edges * KP * 16;
-    for (int i = threadIdx.x; i < n_pm; i += BS) lds[i] = a.pmat[td.pm_off + i];
+    // stage the tree's transition matrices: 16-byte loads, four in flight per
+    // thread (indices clamped into range, so no branch separates the loads)
+    {
+        const int n2 = td.n_edges * KP * 8;
+        const double2 *src = reinterpret_cast<const double2 *>(a.pmat + td.pm_off);
+        double2 *dst = reinterpret_cast<double2 *>(lds);
+        for (int i = threadIdx.x; i < n2; i += 4 * BS) {
+            double2 q[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) q[u] = src[min(i + u * BS, n2 - 1)];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (i + u * BS < n2) dst[i + u * BS] = q[u];
+        }
+    }
     model_to_lds(aln, &model);
     __syncthreads();
     const TreeView<T> v = make_view<T>(td, aln, a, &model, lds);
