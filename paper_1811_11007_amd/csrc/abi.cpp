@@ -302,16 +302,12 @@ pt_status plan_build(pt_ctx *ctx, pt_aln *const *alns, int32_t n_alns, const pt_
         base.edge_off = trees->edge_offset[b];
         base.pm_off = pm_off;
         base.n_tiles = (int)((ad.P + tile_pats - 1) / tile_pats);
-        base.tile_begin = tiles;
+        base.tile_begin = 0;  // assigned below, longest programs first
         clv_off += (int64_t)t.n_slots() * kp * ad.P * 4;
         cnt_off += (int64_t)t.n_slots() * ad.P;
         pm_off += (int64_t)E * kp * 16;
         for (int64_t i = 0; i < E; ++i) edge_tree[base.edge_off + i] = b;
         tll[b] = tgr[b] = top[b] = base;
-        if (kinds & (PT_PLAN_LOGLIK | PT_PLAN_GRAD)) {
-            for (int x = 0; x < base.n_tiles; ++x) tile_tree.push_back(b);
-            tiles += base.n_tiles;
-        }
         if (kinds & PT_PLAN_LOGLIK) {
             std::vector<Op> p;
             pt::compile_loglik(t, p);
@@ -347,6 +343,19 @@ pt_status plan_build(pt_ctx *ctx, pt_aln *const *alns, int32_t n_alns, const pt_
                 ops.insert(ops.end(), p3.begin(), p3.end());
             }
             cost[b] = (double)ad.P * ad.K * (double)(p2.size() + 1);
+        }
+    }
+    if (kinds & (PT_PLAN_LOGLIK | PT_PLAN_GRAD)) {
+        // Tiles of the trees with the longest programs first: the hardware
+        // dispatches blocks in index order, so long tiles start early and the
+        // launch does not end on a tail of them.
+        std::vector<int> order(B);
+        for (int b = 0; b < B; ++b) order[b] = b;
+        std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return pl->tree_E[x] > pl->tree_E[y]; });
+        for (int b : order) {
+            tll[b].tile_begin = tgr[b].tile_begin = top[b].tile_begin = tiles;
+            for (int x = 0; x < tll[b].n_tiles; ++x) tile_tree.push_back(b);
+            tiles += tll[b].n_tiles;
         }
     }
     pl->n_tiles = tiles;

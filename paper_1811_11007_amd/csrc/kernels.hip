@@ -236,12 +236,27 @@ struct Side {
     }
 };
 
+// Transition matrices read by an update: from LDS, or (PM_CONST) from global
+// memory the kernel never writes, through the constant address space, so
+// that the wave-uniform matrix entries arrive by scalar loads into scalar
+// registers instead of being broadcast to every lane.
+template <bool PM_CONST>
+struct PmPtr;
+template <>
+struct PmPtr<false> {
+    using type = const double *;
+};
+template <>
+struct PmPtr<true> {
+    using type = const __attribute__((address_space(4))) double *;
+};
+
 // OP_UPDATE for this thread's patterns, sides of kinds TA / TB (tip or slot):
 //   dst[k] = (P_k(t_ea) . side a[k]) * (P_k(t_eb) . side b[k]), elementwise over
 // states, for every category k, then per-pattern scaling.
-template <typename T, int BS, int KP, bool TA, bool TB>
+template <typename T, int BS, int KP, bool TA, bool TB, bool PM_CONST>
 __device__ inline void update_sides(const TreeView<T> &v, const Op &op, int base, int ni) {
-    const double *pm = v.pm;
+    const typename PmPtr<PM_CONST>::type pm = (typename PmPtr<PM_CONST>::type)v.pm;
     const double thr = ldexp(1.0, -Store<T>::kScaleExp);
     const double up = ldexp(1.0, Store<T>::kScaleExp);
 #pragma unroll 1
@@ -259,8 +274,8 @@ __device__ inline void update_sides(const TreeView<T> &v, const Op &op, int base
             double xa[4], xb[4];
             sa.get(k, xa);
             sb.get(k, xb);
-            const double *Pa = pm + ((size_t)op.ea * KP + k) * 16;
-            const double *Pb = pm + ((size_t)op.eb * KP + k) * 16;
+            const auto Pa = pm + ((size_t)op.ea * KP + k) * 16;
+            const auto Pb = pm + ((size_t)op.eb * KP + k) * 16;
             const bool live = k < v.K;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
@@ -288,14 +303,14 @@ __device__ inline void update_sides(const TreeView<T> &v, const Op &op, int base
 }
 
 // OP_UPDATE for this thread's patterns base + j*BS, j < ni.
-template <typename T, int BS, int KP>
+template <typename T, int BS, int KP, bool PM_CONST = false>
 __device__ inline void do_update(const TreeView<T> &v, const Op &op, int base, int ni) {
     if (op.a < 0) {
-        if (op.b < 0) update_sides<T, BS, KP, true, true>(v, op, base, ni);
-        else update_sides<T, BS, KP, true, false>(v, op, base, ni);
+        if (op.b < 0) update_sides<T, BS, KP, true, true, PM_CONST>(v, op, base, ni);
+        else update_sides<T, BS, KP, true, false, PM_CONST>(v, op, base, ni);
     } else {
-        if (op.b < 0) update_sides<T, BS, KP, false, true>(v, op, base, ni);
-        else update_sides<T, BS, KP, false, false>(v, op, base, ni);
+        if (op.b < 0) update_sides<T, BS, KP, false, true, PM_CONST>(v, op, base, ni);
+        else update_sides<T, BS, KP, false, false, PM_CONST>(v, op, base, ni);
     }
 }
 
@@ -586,12 +601,16 @@ __global__ void __launch_bounds__(BS) k_tiles(const BatchArgs a, const double *b
     __shared__ double red[2 * (BS / 64) * 3];
     __shared__ double wxs[(BS / 64) * kWx];
     __shared__ ModelS model;
+    // FP32 partials: the updates read the tree's transition matrices (written
+    // by k_pmat before this launch) in place by scalar loads (see PmPtr);
+    // FP64 partials: from a copy in LDS, which measured faster there.
+    constexpr bool kPmConst = std::is_same<T, float>::value;
     const int tile = blockIdx.x;
     const TreeDev td = a.trees[a.tile_tree[tile]];
     const AlnDev *aln = a.alns + td.aln;
-    // stage the tree's transition matrices: 16-byte loads, four in flight per
-    // thread (indices clamped into range, so no branch separates the loads)
-    {
+    if (!kPmConst) {
+        // 16-byte loads, four in flight per thread (indices clamped into
+        // range, so no branch separates the loads)
         const int n2 = td.n_edges * KP * 8;
         const double2 *src = reinterpret_cast<const double2 *>(a.pmat + td.pm_off);
         double2 *dst = reinterpret_cast<double2 *>(lds);
@@ -606,14 +625,14 @@ __global__ void __launch_bounds__(BS) k_tiles(const BatchArgs a, const double *b
     }
     model_to_lds(aln, &model);
     __syncthreads();
-    const TreeView<T> v = make_view<T>(td, aln, a, &model, lds);
+    const TreeView<T> v = make_view<T>(td, aln, a, &model, kPmConst ? a.pmat + td.pm_off : lds);
     double *wx = wxs + (threadIdx.x >> 6) * kWx;
     const int base = (tile - td.tile_begin) * BS * kTileItems;
     int parity = 0;
     for (int o = 0; o < td.n_first; ++o) {
         const Op op = a.ops[td.op_first + o];
         if (op.code == OP_UPDATE) {
-            do_update<T, BS, KP>(v, op, base, kTileItems);
+            do_update<T, BS, KP, kPmConst>(v, op, base, kTileItems);
             continue;
         }
         const Sums3 r =
@@ -852,6 +871,7 @@ size_t spill_opt_t() {
 
 template <typename T, int BS, int KP>
 hipError_t launch_tiles_t(const BatchArgs &a, const double *brlen, size_t lds, hipStream_t s) {
+    if (std::is_same<T, float>::value) lds = 0;
     if (lds > 48 * 1024) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_tiles<T, BS, KP>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

@@ -45,8 +45,9 @@ size_t optimize_spill_bytes(int precision, int block, int kp, bool tab_lds);
 
 hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
 hipError_t launch_pmat(const BatchArgs &a, const double *brlen, hipStream_t s);
-hipError_t launch_tiles(int precision, int kp, const BatchArgs &a, const double *brlen,
-                        size_t lds_bytes, hipStream_t s);
+// lds_bytes: the largest tree's transition matrices (used with FP64 partials).
+hipError_t launch_tiles(int precision, int kp, const BatchArgs &a, const double *brlen, size_t lds_bytes,
+                        hipStream_t s);
 hipError_t launch_reduce(bool grad, const BatchArgs &a, double *lnl, double *grad_out,
                          double *hess_out, hipStream_t s);
 hipError_t launch_optimize(int precision, int block, int kp, int items, bool tab_lds, int pm_doubles, int grid,
