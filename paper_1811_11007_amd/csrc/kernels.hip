@@ -415,29 +415,106 @@ __device__ inline double table_sides(const TreeView<T> &v, int a, int b, int ni,
                                      double logK) {
     const ModelS *md = v.m;
     double cterm = 0.0;
+    // two patterns per step (FP32 partials; with FP64 the registers of a
+    // second pattern would spill), both fetched before either is used; a
+    // missing second pattern re-reads the first (in bounds) and is not stored
+    constexpr int kStep = std::is_same<T, float>::value ? 2 : 1;
 #pragma unroll 1
-    for (int j = 0; j < ni; ++j) {
-        const int p = j * BS + threadIdx.x;
-        if (p >= v.P) break;
-        Side<T, KP, TA> sa;
-        Side<T, KP, TB> sb;
-        sa.fetch(v, a, p);
-        sb.fetch(v, b, p);
-        const double w = ldg(v.w + p);
-        cterm += w * const_term<T>(sa.c + sb.c, logK);
-        wrow[j * BS + threadIdx.x] = w;
+    for (int j = 0; j < ni; j += kStep) {
+        const int p0 = j * BS + threadIdx.x;
+        if (p0 >= v.P) break;
+        const bool two = kStep == 2 && j + 1 < ni && p0 + BS < v.P;
+        const int p1 = two ? p0 + BS : p0;
+        Side<T, KP, TA> sa0, sa1;
+        Side<T, KP, TB> sb0, sb1;
+        sa0.fetch(v, a, p0);
+        sb0.fetch(v, b, p0);
+        sa1.fetch(v, a, p1);
+        sb1.fetch(v, b, p1);
+        const double w0 = ldg(v.w + p0), w1 = ldg(v.w + p1);
+        cterm += w0 * const_term<T>(sa0.c + sb0.c, logK);
+        wrow[p0] = w0;
 #pragma unroll
         for (int k = 0; k < KP; ++k) {
             if (k < v.K) {
                 double xa[4], xb[4], sk[4];
-                sa.get(k, xa);
-                sb.get(k, xb);
+                sa0.get(k, xa);
+                sb0.get(k, xb);
                 coeffs_x(md, xa, xb, sk);
-                Store<T>::store(tab + ((size_t)k * rows + j * BS + threadIdx.x) * 4, sk);
+                Store<T>::store(tab + ((size_t)k * rows + p0) * 4, sk);
+            }
+        }
+        if (two) {
+            cterm += w1 * const_term<T>(sa1.c + sb1.c, logK);
+            wrow[p1] = w1;
+#pragma unroll
+            for (int k = 0; k < KP; ++k) {
+                if (k < v.K) {
+                    double xa[4], xb[4], sk[4];
+                    sa1.get(k, xa);
+                    sb1.get(k, xb);
+                    coeffs_x(md, xa, xb, sk);
+                    Store<T>::store(tab + ((size_t)k * rows + p1) * 4, sk);
+                }
             }
         }
     }
     return cterm;
+}
+
+// Newton pass over two table rows r0 and r1 (r1 < 0: only r0), so that each
+// exponential read from the wave's LDS slice serves two patterns.  Adds the
+// rows' d1 and d2 terms, or with lnl_only their weighted log L to d0; each
+// row's sums run in the same order as for a single row.
+template <typename T, int KP>
+__device__ inline void newton_rows2(const T *tab, const double *wrow, size_t rows, int r0, int r1, const double *wx,
+                                    int K, bool lnl_only, double &d0, double &d1, double &d2) {
+    using Raw = typename Store<T>::Raw;
+    const bool two = r1 >= 0;
+    const int rb = two ? r1 : r0;
+    Raw ra[KP], rr[KP];
+#pragma unroll
+    for (int k = 0; k < KP; ++k) {
+        if (k < K) {
+            ra[k] = Store<T>::load_raw(tab + ((size_t)k * rows + r0) * 4);
+            rr[k] = Store<T>::load_raw(tab + ((size_t)k * rows + rb) * 4);
+        }
+    }
+    const double wa = wrow[r0], wb = wrow[rb];
+    double La = 0.0, L1a = 0.0, L2a = 0.0, Lb = 0.0, L1b = 0.0, L2b = 0.0;
+#pragma unroll
+    for (int k = 0; k < KP; ++k) {
+        if (k < K) {
+            double sa[4], sb[4];
+            Store<T>::widen(ra[k], sa);
+            Store<T>::widen(rr[k], sb);
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const double e0 = wx[k * 4 + m], e1 = wx[4 * kMaxCats + k * 4 + m], e2 = wx[8 * kMaxCats + k * 4 + m];
+                La += sa[m] * e0;
+                L1a += sa[m] * e1;
+                L2a += sa[m] * e2;
+                Lb += sb[m] * e0;
+                L1b += sb[m] * e1;
+                L2b += sb[m] * e2;
+            }
+        }
+    }
+    if (lnl_only) {
+        d0 += wa * log(La);
+        if (two) d0 += wb * log(Lb);
+        return;
+    }
+    const double ia = recip(La);
+    const double ra1 = L1a * ia;
+    d1 += wa * ra1;
+    d2 += wa * (L2a * ia - ra1 * ra1);
+    if (two) {
+        const double ib = recip(Lb);
+        const double rb1 = L1b * ib;
+        d1 += wb * rb1;
+        d2 += wb * (L2b * ib - rb1 * rb1);
+    }
 }
 
 // OP_NEWTON: safeguarded, projected Newton on the length of one edge.
@@ -471,6 +548,8 @@ __device__ inline EdgeResult newton_edge(const TreeView<T> &v, int a, int b, dou
         if (b < 0) cterm = table_sides<T, BS, KP, false, true>(v, a, b, ni, rows, tab, wrow, logK);
         else cterm = table_sides<T, BS, KP, false, false>(v, a, b, ni, rows, tab, wrow, logK);
     }
+    // rows this thread owns: tid + j*BS < P
+    const int nj = v.P > (int)threadIdx.x ? min(ni, (v.P - (int)threadIdx.x + BS - 1) / BS) : 0;
     const long long c1 = clock64();
     double lo = opt.t_min, hi = opt.t_max;
     int iter = 1;
@@ -478,30 +557,9 @@ __device__ inline EdgeResult newton_edge(const TreeView<T> &v, int a, int b, dou
         wave_expo(wx, v.m, v.K, t);
         double d0 = 0.0, d1 = 0.0, d2 = 0.0;
 #pragma unroll 1
-        for (int j = 0; j < ni; ++j) {
-            const int p = j * BS + threadIdx.x;
-            if (p >= v.P) break;
-            double s[KP][4];
-#pragma unroll
-            for (int k = 0; k < KP; ++k) Store<T>::load(tab + ((size_t)k * rows + j * BS + threadIdx.x) * 4, s[k]);
-            const double w = wrow[j * BS + threadIdx.x];
-            double L = 0.0, L1 = 0.0, L2 = 0.0;
-#pragma unroll
-            for (int k = 0; k < KP; ++k) {
-                if (k < v.K) {
-#pragma unroll
-                    for (int m = 0; m < 4; ++m) {
-                        L += s[k][m] * wx[k * 4 + m];
-                        L1 += s[k][m] * wx[4 * kMaxCats + k * 4 + m];
-                        L2 += s[k][m] * wx[8 * kMaxCats + k * 4 + m];
-                    }
-                }
-            }
-            const double inv = recip(L);
-            const double r1 = L1 * inv;
-            d1 += w * r1;
-            d2 += w * (L2 * inv - r1 * r1);
-        }
+        for (int j = 0; j < nj; j += 2)
+            newton_rows2<T, KP>(tab, wrow, rows, j * BS + threadIdx.x, j + 1 < nj ? (j + 1) * BS + threadIdx.x : -1,
+                                wx, v.K, false, d0, d1, d2);
         block_sum3<BS>(d0, d1, d2, red, parity);
         if (iter >= opt.max_newton) break;
         if (d1 > 0.0) lo = t;
@@ -522,20 +580,9 @@ __device__ inline EdgeResult newton_edge(const TreeView<T> &v, int a, int b, dou
         wave_expo(wx, v.m, v.K, t);
         double l0 = cterm, z1 = 0.0, z2 = 0.0;
 #pragma unroll 1
-        for (int j = 0; j < ni; ++j) {
-            const int p = j * BS + threadIdx.x;
-            if (p >= v.P) break;
-            double s[KP][4];
-#pragma unroll
-            for (int k = 0; k < KP; ++k) Store<T>::load(tab + ((size_t)k * rows + j * BS + threadIdx.x) * 4, s[k]);
-            double L = 0.0;
-#pragma unroll
-            for (int k = 0; k < KP; ++k)
-                if (k < v.K)
-#pragma unroll
-                    for (int m = 0; m < 4; ++m) L += s[k][m] * wx[k * 4 + m];
-            l0 += wrow[j * BS + threadIdx.x] * log(L);
-        }
+        for (int j = 0; j < nj; j += 2)
+            newton_rows2<T, KP>(tab, wrow, rows, j * BS + threadIdx.x, j + 1 < nj ? (j + 1) * BS + threadIdx.x : -1,
+                                wx, v.K, true, l0, z1, z2);
         block_sum3<BS>(l0, z1, z2, red, parity);
         lnl = l0;
     }
