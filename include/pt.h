@@ -99,7 +99,9 @@ typedef struct {
 
 /* Branch-length optimisation settings.  Per edge: safeguarded Newton on
  * t in [t_min, t_max], at most max_newton derivative evaluations, stopping
- * when a step would move t by at most tol_newton * max(t, 1e-6).  Per tree:
+ * when a step would move t by at most tol_newton * max(t, 1e-6) (not taken),
+ * or after taking a Newton step of at most sqrt(tol_newton) * max(t, 1e-6)
+ * (quadratic convergence leaves an error of order tol_newton).  Per tree:
  * passes over the masked edges until a pass raises lnL by less than tol_lnl
  * and changes no length by more than tol_t relative, or max_passes. */
 typedef struct {

@@ -528,7 +528,9 @@ __device__ inline void newton_rows2(const T *tab, const double *wrow, size_t row
 //    original bounds count as inside), else the bracket is bisected
 //    geometrically;
 //  - a bound with the derivative pointing outwards is an optimum;
-//  - a step of at most tol * max(t, 1e-6) is converged and not taken;
+//  - a step of at most tol * max(t, 1e-6) is converged and not taken; a
+//    Newton step of at most sqrt(tol) * max(t, 1e-6) is taken and ends the
+//    edge (quadratic convergence leaves an error of order tol);
 //  - with want_lnl, lnL is evaluated at the returned t.
 // All threads hold identical block totals, so every thread takes the same
 // decisions.
@@ -572,8 +574,14 @@ __device__ inline EdgeResult newton_edge(const TreeView<T> &v, int a, int b, dou
         const bool inside = !isnan(tn) && (tn > lo || (lo == opt.t_min && tn == opt.t_min)) &&
                             (tn < hi || (hi == opt.t_max && tn == opt.t_max));
         if (!inside) tn = sqrt(lo * hi);
-        if (fabs(tn - t) <= opt.tol_newton * fmax(t, 1e-6)) break;
+        const double dt = fabs(tn - t), scale = fmax(t, 1e-6);
+        if (dt <= opt.tol_newton * scale) break;
         t = tn;
+        // Newton converges quadratically near the optimum: after a Newton
+        // step of relative size below sqrt(tol_newton) the remaining error is
+        // of order tol_newton, so the step is taken without a confirming
+        // evaluation.
+        if (inside && dt <= sqrt(opt.tol_newton) * scale) break;
     }
     double lnl = 0.0;
     if (want_lnl) {
