@@ -418,7 +418,11 @@ pt_status plan_build(pt_ctx *ctx, pt_aln *const *alns, int32_t n_alns, const pt_
         const AlnDev &a2 = alns[trees->aln_index[b]]->desc;
         (void)a2;
         pl->lds_tiles = std::max(pl->lds_tiles, (size_t)pl->tree_E[b] * kp * 16 * 8);
-        pl->pm_doubles = std::max(pl->pm_doubles, pl->tree_E[b] * (kp * 16 + 1));
+        // matrices and lengths, then (FP32 partials) an FP32 copy of the
+        // matrices on a 16-byte boundary
+        const int E = pl->tree_E[b];
+        const int dbl = E * (kp * 16 + 1);
+        pl->pm_doubles = std::max(pl->pm_doubles, precision == PT_FP32 ? ((dbl + 1) & ~1) + E * kp * 8 : dbl);
     }
     pl->pm_doubles = (pl->pm_doubles + 3) / 4 * 4;  // 32-byte aligned table rows after it
     if (kinds & PT_PLAN_OPTIMIZE) {

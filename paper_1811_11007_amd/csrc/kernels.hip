@@ -103,7 +103,8 @@ __device__ inline X ldg(const X *p) {
 template <typename T>
 struct TreeView {
     const ModelS *m;     // LDS
-    const double *pm;    // LDS: [E][Kp][16]
+    const double *pm;    // LDS: [E][Kp][16] (or global, see PmPtr)
+    const float *pmf;    // optional FP32 copy of pm in LDS
     const uint8_t *tips; // [n][P]
     const double *w;     // [P]
     T *clv;              // slot 0 of this tree: [slot][Kp][P][4]
@@ -236,27 +237,39 @@ struct Side {
     }
 };
 
-// Transition matrices read by an update: from LDS, or (PM_CONST) from global
-// memory the kernel never writes, through the constant address space, so
-// that the wave-uniform matrix entries arrive by scalar loads into scalar
-// registers instead of being broadcast to every lane.
-template <bool PM_CONST>
-struct PmPtr;
-template <>
-struct PmPtr<false> {
+// Where an update reads its transition matrices (PM):
+//   kPmLds    FP64 copy in LDS;
+//   kPmConst  global memory the kernel never writes, through the constant
+//             address space, so that the wave-uniform entries arrive by
+//             scalar loads into scalar registers instead of being broadcast
+//             to every lane;
+//   kPmLds32  FP32 copy in LDS (half the broadcast bytes), for FP32 partials
+//             in the optimisation loop.
+enum : int { kPmLds = 0, kPmConst = 1, kPmLds32 = 2 };
+template <int PM>
+struct PmPtr {
     using type = const double *;
 };
 template <>
-struct PmPtr<true> {
+struct PmPtr<kPmConst> {
     using type = const __attribute__((address_space(4))) double *;
 };
+template <>
+struct PmPtr<kPmLds32> {
+    using type = const float *;
+};
+template <int PM, typename V>
+__device__ inline typename PmPtr<PM>::type pm_base(const V &v) {
+    if constexpr (PM == kPmLds32) return v.pmf;
+    else return (typename PmPtr<PM>::type)v.pm;
+}
 
 // OP_UPDATE for this thread's patterns, sides of kinds TA / TB (tip or slot):
 //   dst[k] = (P_k(t_ea) . side a[k]) * (P_k(t_eb) . side b[k]), elementwise over
 // states, for every category k, then per-pattern scaling.
-template <typename T, int BS, int KP, bool TA, bool TB, bool PM_CONST>
+template <typename T, int BS, int KP, bool TA, bool TB, int PM>
 __device__ inline void update_sides(const TreeView<T> &v, const Op &op, int base, int ni) {
-    const typename PmPtr<PM_CONST>::type pm = (typename PmPtr<PM_CONST>::type)v.pm;
+    const auto pm = pm_base<PM>(v);
     const double thr = ldexp(1.0, -Store<T>::kScaleExp);
     const double up = ldexp(1.0, Store<T>::kScaleExp);
 #pragma unroll 1
@@ -303,14 +316,14 @@ __device__ inline void update_sides(const TreeView<T> &v, const Op &op, int base
 }
 
 // OP_UPDATE for this thread's patterns base + j*BS, j < ni.
-template <typename T, int BS, int KP, bool PM_CONST = false>
+template <typename T, int BS, int KP, int PM = kPmLds>
 __device__ inline void do_update(const TreeView<T> &v, const Op &op, int base, int ni) {
     if (op.a < 0) {
-        if (op.b < 0) update_sides<T, BS, KP, true, true, PM_CONST>(v, op, base, ni);
-        else update_sides<T, BS, KP, true, false, PM_CONST>(v, op, base, ni);
+        if (op.b < 0) update_sides<T, BS, KP, true, true, PM>(v, op, base, ni);
+        else update_sides<T, BS, KP, true, false, PM>(v, op, base, ni);
     } else {
-        if (op.b < 0) update_sides<T, BS, KP, false, true, PM_CONST>(v, op, base, ni);
-        else update_sides<T, BS, KP, false, false, PM_CONST>(v, op, base, ni);
+        if (op.b < 0) update_sides<T, BS, KP, false, true, PM>(v, op, base, ni);
+        else update_sides<T, BS, KP, false, false, PM>(v, op, base, ni);
     }
 }
 
@@ -610,6 +623,7 @@ __device__ inline TreeView<T> make_view(const TreeDev &td, const AlnDev *aln, co
     TreeView<T> v;
     v.m = m;
     v.pm = pm_lds;
+    v.pmf = nullptr;
     v.tips = aln->tips;
     v.w = aln->w;
     v.clv = reinterpret_cast<T *>(a.clv) + td.clv_off;
@@ -659,11 +673,11 @@ __global__ void __launch_bounds__(BS) k_tiles(const BatchArgs a, const double *b
     // FP32 partials: the updates read the tree's transition matrices (written
     // by k_pmat before this launch) in place by scalar loads (see PmPtr);
     // FP64 partials: from a copy in LDS, which measured faster there.
-    constexpr bool kPmConst = std::is_same<T, float>::value;
+    constexpr bool kConstPm = std::is_same<T, float>::value;
     const int tile = blockIdx.x;
     const TreeDev td = a.trees[a.tile_tree[tile]];
     const AlnDev *aln = a.alns + td.aln;
-    if (!kPmConst) {
+    if (!kConstPm) {
         // 16-byte loads, four in flight per thread (indices clamped into
         // range, so no branch separates the loads)
         const int n2 = td.n_edges * KP * 8;
@@ -680,14 +694,14 @@ __global__ void __launch_bounds__(BS) k_tiles(const BatchArgs a, const double *b
     }
     model_to_lds(aln, &model);
     __syncthreads();
-    const TreeView<T> v = make_view<T>(td, aln, a, &model, kPmConst ? a.pmat + td.pm_off : lds);
+    const TreeView<T> v = make_view<T>(td, aln, a, &model, kConstPm ? a.pmat + td.pm_off : lds);
     double *wx = wxs + (threadIdx.x >> 6) * kWx;
     const int base = (tile - td.tile_begin) * BS * kTileItems;
     int parity = 0;
     for (int o = 0; o < td.n_first; ++o) {
         const Op op = a.ops[td.op_first + o];
         if (op.code == OP_UPDATE) {
-            do_update<T, BS, KP, kPmConst>(v, op, base, kTileItems);
+            do_update<T, BS, KP, kConstPm ? kPmConst : kPmLds>(v, op, base, kTileItems);
             continue;
         }
         const Sums3 r =
@@ -766,15 +780,21 @@ __global__ void __launch_bounds__(BS) k_optimize(const BatchArgs a, double *brle
         const int E = td.n_edges;
         double *pm = lds;
         double *tl = lds + (size_t)E * KP * 16;
+        // FP32 partials: an FP32 copy of the matrices for the loop's updates,
+        // 16-byte aligned after the lengths
+        constexpr bool kF32 = std::is_same<T, float>::value;
+        float *pmf = reinterpret_cast<float *>(lds + (((size_t)E * KP * 16 + E + 1) & ~(size_t)1));
         for (int e = tid; e < E; e += BS) tl[e] = fmin(fmax(brlen[td.edge_off + e], opt.t_min), opt.t_max);
         model_to_lds(aln, &model);
         __syncthreads();
         for (int x = tid; x < E * KP * 16; x += BS) {
             const int e = x / (KP * 16), r = x % (KP * 16);
             pm[x] = pm_entry(aln, r >> 4, r & 15, tl[e]);
+            if (kF32) pmf[x] = (float)pm[x];
         }
         __syncthreads();
-        const TreeView<T> v = make_view<T>(td, aln, a, &model, pm);
+        TreeView<T> v = make_view<T>(td, aln, a, &model, pm);
+        v.pmf = pmf;
         int parity = 0;
         double prev = -INFINITY, cur = -INFINITY;
         int passes = 0;
@@ -790,7 +810,7 @@ __global__ void __launch_bounds__(BS) k_optimize(const BatchArgs a, double *brle
                 const Op op = a.ops[o0 + o];
                 if (op.code == OP_UPDATE) {
                     const long long u0 = a.prof ? clock64() : 0;
-                    do_update<T, BS, KP>(v, op, 0, ni);
+                    do_update<T, BS, KP, kF32 ? kPmLds32 : kPmLds>(v, op, 0, ni);
                     if (a.prof) {
                         pc[PROF_UPDATES] += 1;
                         pc[PROF_CYC_UPDATE] += clock64() - u0;
@@ -817,7 +837,11 @@ __global__ void __launch_bounds__(BS) k_optimize(const BatchArgs a, double *brle
                 max_rel = fmax(max_rel, fabs(r.t - t0) / fmax(t0, 1e-6));
                 if (r.t != t0) {
                     if (tid == 0) tl[e] = r.t;
-                    if (tid < KP * 16) pm[(size_t)e * KP * 16 + tid] = pm_entry(aln, tid >> 4, tid & 15, r.t);
+                    if (tid < KP * 16) {
+                        const double pe = pm_entry(aln, tid >> 4, tid & 15, r.t);
+                        pm[(size_t)e * KP * 16 + tid] = pe;
+                        if (kF32) pmf[(size_t)e * KP * 16 + tid] = (float)pe;
+                    }
                     __syncthreads();
                 }
             }
