@@ -237,6 +237,9 @@ pt_status pt_nni_neighbors(int32_t n, const int32_t *edges, const double *brlen,
  * sorted ascending (as W-word numbers, most significant word last).
  * out: uint64[n-3][W].  Equal keys <=> equal unrooted topologies.  n >= 4. */
 pt_status pt_topology_key(int32_t n, const int32_t *edges, uint64_t *out);
+/* The keys of `count` trees on n taxa at once: edges int32[count][2n-3][2],
+ * out uint64[count][n-3][W].  On error nothing is guaranteed about out. */
+pt_status pt_topology_keys(int32_t n, int32_t count, const int32_t *edges, uint64_t *out);
 
 /* -------------------------------------------- warm-start network (learned) */
 

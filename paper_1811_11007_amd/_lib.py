@@ -24,7 +24,8 @@ EXPORTS = [
     "pt_opt_default", "pt_batch_loglik", "pt_batch_optimize_branches", "pt_batch_branch_grad",
     "pt_plan_create", "pt_plan_destroy", "pt_plan_set_graphs", "pt_plan_loglik",
     "pt_plan_optimize", "pt_plan_grad", "pt_plan_autotune", "pt_plan_traffic", "pt_plan_set_profile", "pt_plan_info",
-    "pt_model_info", "pt_tree_check", "pt_nni_neighbors", "pt_topology_key", "pt_nni_features",
+    "pt_model_info", "pt_tree_check", "pt_nni_neighbors", "pt_topology_key", "pt_topology_keys",
+    "pt_nni_features",
     "pt_mlp_create", "pt_mlp_destroy", "pt_mlp_param_count", "pt_mlp_get_params", "pt_mlp_set_params",
     "pt_mlp_forward", "pt_mlp_warm_start", "pt_mlp_gradient", "pt_mlp_train_step",
 ]
@@ -108,6 +109,7 @@ def lib():
         L.pt_tree_check.argtypes = [i32, vp]
         L.pt_nni_neighbors.argtypes = [i32, vp, vp, vp, vp, vp]
         L.pt_topology_key.argtypes = [i32, vp, vp]
+        L.pt_topology_keys.argtypes = [i32, i32, vp, vp]
         L.pt_nni_features.argtypes = [i32, vp, vp, vp]
         L.pt_mlp_create.argtypes = [vp, i32, i32, i32, vp, P(vp)]
         L.pt_mlp_destroy.argtypes = [vp]
@@ -296,6 +298,16 @@ def pt_topology_key(n, edges):
     W = (n + 63) // 64
     out = np.zeros((max(n - 3, 0), W), np.uint64)
     check(lib().pt_topology_key(n, _ptr(e), _ptr(out)))
+    return out
+
+
+def pt_topology_keys(n, edges):
+    """Keys of a stack of trees: edges [count][2n-3][2] -> uint64[count][n-3][W]."""
+    e = np.ascontiguousarray(edges, dtype=np.int32)
+    count = e.shape[0]
+    W = (n + 63) // 64
+    out = np.zeros((count, max(n - 3, 0), W), np.uint64)
+    check(lib().pt_topology_keys(int(n), int(count), _ptr(e), _ptr(out)))
     return out
 
 

@@ -952,6 +952,17 @@ pt_status pt_topology_key(int32_t n, const int32_t *edges, uint64_t *out) {
     return st ? fail(st, err) : PT_OK;
 }
 
+pt_status pt_topology_keys(int32_t n, int32_t count, const int32_t *edges, uint64_t *out) {
+    if (count < 0 || (count > 0 && (!edges || !out))) return fail(PT_EINVAL, "bad arguments");
+    const size_t E = n >= 2 ? (size_t)(2 * n - 3) : 0, W = (size_t)(n + 63) / 64;
+    std::string err;
+    for (int32_t i = 0; i < count; ++i) {
+        pt_status st = pt::topology_key(n, edges + i * E * 2, out + i * (size_t)(n > 3 ? n - 3 : 0) * W, err);
+        if (st) return fail(st, "tree " + std::to_string(i) + ": " + err);
+    }
+    return PT_OK;
+}
+
 pt_status pt_nni_features(int32_t n, const int32_t *edges, const double *brlen, float *out) {
     if (!edges || !brlen || !out) return fail(PT_EINVAL, "NULL argument");
     std::string err;

@@ -327,10 +327,13 @@ pt_status topology_key(int n, const int32_t *edges, uint64_t *out, std::string &
     pt_status st = build_tree(n, edges, t, err);
     if (st) return st;
     const int W = (n + 63) / 64;
-    // iterative post-order from leaf 0: leaf set below every node
-    std::vector<std::vector<uint64_t>> below(t.n_nodes, std::vector<uint64_t>(W, 0));
-    std::vector<int> parent(t.n_nodes, -1), order;
-    std::vector<int> stack{0};
+    // iterative depth-first order from leaf 0, then leaf sets bottom-up
+    // (flat arrays: one allocation each)
+    std::vector<uint64_t> below((size_t)t.n_nodes * W, 0);
+    std::vector<int> parent(t.n_nodes, -1), order, stack;
+    order.reserve(t.n_nodes);
+    stack.reserve(t.n_nodes);
+    stack.push_back(0);
     parent[0] = 0;
     while (!stack.empty()) {
         int v = stack.back();
@@ -341,23 +344,35 @@ pt_status topology_key(int n, const int32_t *edges, uint64_t *out, std::string &
             if (parent[c] < 0 && c != 0) { parent[c] = v; stack.push_back(c); }
         }
     }
-    std::vector<std::vector<uint64_t>> splits;
+    std::vector<uint64_t> splits;
+    splits.reserve((size_t)(n - 3) * W);
     for (int i = (int)order.size() - 1; i >= 1; --i) {
-        int v = order[i];
-        if (v < n) below[v][v / 64] |= 1ull << (v % 64);
+        const int v = order[i];
+        uint64_t *bv = below.data() + (size_t)v * W;
+        if (v < n) bv[v / 64] |= 1ull << (v % 64);
         int cnt = 0;
-        for (int w = 0; w < W; ++w) cnt += __builtin_popcountll(below[v][w]);
-        if (cnt >= 2 && cnt <= n - 2) splits.push_back(below[v]);
-        for (int w = 0; w < W; ++w) below[parent[v]][w] |= below[v][w];
+        for (int w = 0; w < W; ++w) cnt += __builtin_popcountll(bv[w]);
+        if (cnt >= 2 && cnt <= n - 2) splits.insert(splits.end(), bv, bv + W);
+        uint64_t *bp = below.data() + (size_t)parent[v] * W;
+        for (int w = 0; w < W; ++w) bp[w] |= bv[w];
     }
-    if ((int)splits.size() != n - 3) { err = "internal error: split count"; return PT_EINTERNAL; }
-    std::sort(splits.begin(), splits.end(), [W](const std::vector<uint64_t> &a, const std::vector<uint64_t> &b) {
-        for (int w = W - 1; w >= 0; --w)
-            if (a[w] != b[w]) return a[w] < b[w];
+    if ((int)(splits.size() / W) != n - 3) { err = "internal error: split count"; return PT_EINTERNAL; }
+    if (W == 1) {
+        std::sort(splits.begin(), splits.end());
+        std::copy(splits.begin(), splits.end(), out);
+        return PT_OK;
+    }
+    std::vector<int> idx(n - 3);
+    for (int i = 0; i < n - 3; ++i) idx[i] = i;
+    std::sort(idx.begin(), idx.end(), [&](int x, int y) {
+        for (int w = W - 1; w >= 0; --w) {
+            const uint64_t a = splits[(size_t)x * W + w], b = splits[(size_t)y * W + w];
+            if (a != b) return a < b;
+        }
         return false;
     });
     for (int i = 0; i < n - 3; ++i)
-        for (int w = 0; w < W; ++w) out[(size_t)i * W + w] = splits[i][w];
+        for (int w = 0; w < W; ++w) out[(size_t)i * W + w] = splits[(size_t)idx[i] * W + w];
     return PT_OK;
 }
 

@@ -158,8 +158,9 @@ class ThresholdSearch:
             for e, b in parents:
                 ne, nb, tt = L.pt_nni_neighbors(n, e, b)
                 F = L.pt_nni_features(n, e, b) if (self.warm is not None or collect) else None
+                ks = L.pt_topology_keys(n, ne)
                 for j in range(len(ne)):
-                    k = self.key(ne[j])
+                    k = ks[j].tobytes()
                     if k in visited or k in queued:
                         continue
                     queued.add(k)
@@ -183,11 +184,9 @@ class ThresholdSearch:
                 starts = np.concatenate([p[2] for p in chunk])
                 masks = None
                 if radius == 0:
-                    masks = []
-                    for p in chunk:
-                        m = np.zeros(E, np.uint8)
-                        m[p[4][0]] = 1
-                        masks.append(m)
+                    m = np.zeros((nc, E), np.uint8)
+                    m[np.arange(nc), [p[4][0] for p in chunk]] = 1
+                    masks = list(m)
                 warm_rows = None
                 if dual:
                     X = np.stack([p[3] for p in chunk]).astype(np.float32)
