@@ -199,7 +199,7 @@ int64_t tree_bytes(int n, const AlnDev &a, int precision, int kinds) {
 
 // Static LDS of the optimisation kernel at 512 threads (reduction buffers,
 // per-wave exponential tables, model, counter), rounded up.
-constexpr size_t kOptStaticLds = 8192;
+constexpr size_t kOptStaticLds = 12288;
 
 // Sets the optimisation launch shape for `block` threads per block: patterns
 // per thread, where the eigenbasis table lives (LDS when it fits, else a

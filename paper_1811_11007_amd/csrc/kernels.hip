@@ -197,7 +197,7 @@ __device__ inline void block_sum3(double &a, double &b, double &c, double *red, 
 // wave complete in order, so the wave's later reads see them.
 constexpr int kWx = 3 * 4 * kMaxCats;  // doubles per wave
 
-__device__ inline void wave_expo(double *wx, const ModelS *md, int K, double t) {
+__device__ inline void wave_expo(double *wx, const ModelS *md, int K, double t, float *wxf = nullptr) {
     const int lane = threadIdx.x & 63;
     if (lane < 4 * K) {
         const int k = lane >> 2, m = lane & 3;
@@ -206,6 +206,11 @@ __device__ inline void wave_expo(double *wx, const ModelS *md, int K, double t) 
         wx[lane] = e;
         wx[4 * kMaxCats + lane] = e * q;
         wx[8 * kMaxCats + lane] = e * q * q;
+        if (wxf) {
+            wxf[lane] = (float)e;
+            wxf[4 * kMaxCats + lane] = (float)(e * q);
+            wxf[8 * kMaxCats + lane] = (float)(e * q * q);
+        }
     }
     __builtin_amdgcn_wave_barrier();
 }
@@ -479,8 +484,8 @@ __device__ inline double table_sides(const TreeView<T> &v, int a, int b, int ni,
 // exponential read from the wave's LDS slice serves two patterns.  Adds the
 // rows' d1 and d2 terms, or with lnl_only their weighted log L to d0; each
 // row's sums run in the same order as for a single row.
-template <typename T, int KP>
-__device__ inline void newton_rows2(const T *tab, const double *wrow, size_t rows, int r0, int r1, const double *wx,
+template <typename T, int KP, typename X>
+__device__ inline void newton_rows2(const T *tab, const double *wrow, size_t rows, int r0, int r1, const X *wx,
                                     int K, bool lnl_only, double &d0, double &d1, double &d2) {
     using Raw = typename Store<T>::Raw;
     const bool two = r1 >= 0;
@@ -503,7 +508,8 @@ __device__ inline void newton_rows2(const T *tab, const double *wrow, size_t row
             Store<T>::widen(rr[k], sb);
 #pragma unroll
             for (int m = 0; m < 4; ++m) {
-                const double e0 = wx[k * 4 + m], e1 = wx[4 * kMaxCats + k * 4 + m], e2 = wx[8 * kMaxCats + k * 4 + m];
+                const double e0 = wx[k * 4 + m], e1 = wx[4 * kMaxCats + k * 4 + m],
+                             e2 = wx[8 * kMaxCats + k * 4 + m];
                 La += sa[m] * e0;
                 L1a += sa[m] * e1;
                 L2a += sa[m] * e2;
@@ -550,7 +556,7 @@ __device__ inline void newton_rows2(const T *tab, const double *wrow, size_t row
 template <typename T, int BS, int KP>
 __device__ inline EdgeResult newton_edge(const TreeView<T> &v, int a, int b, double t, bool want_lnl,
                                          const OptParams &opt, T *tab, double *wrow, int ni, double *red,
-                                         double *wx, int parity) {
+                                         double *wx, float *wxf, int parity) {
     const ModelS *md = v.m;
     const size_t rows = (size_t)BS * ni;
     const double logK = log((double)v.K);
@@ -569,12 +575,24 @@ __device__ inline EdgeResult newton_edge(const TreeView<T> &v, int a, int b, dou
     double lo = opt.t_min, hi = opt.t_max;
     int iter = 1;
     for (;; ++iter) {
-        wave_expo(wx, v.m, v.K, t);
         double d0 = 0.0, d1 = 0.0, d2 = 0.0;
+        if constexpr (std::is_same<T, float>::value) {
+            // FP32 partials: FP32 exponentials suffice for the derivatives
+            // (they only steer Newton); lnL below uses FP64 ones
+            wave_expo(wx, v.m, v.K, t, wxf);
 #pragma unroll 1
-        for (int j = 0; j < nj; j += 2)
-            newton_rows2<T, KP>(tab, wrow, rows, j * BS + threadIdx.x, j + 1 < nj ? (j + 1) * BS + threadIdx.x : -1,
-                                wx, v.K, false, d0, d1, d2);
+            for (int j = 0; j < nj; j += 2)
+                newton_rows2<T, KP>(tab, wrow, rows, j * BS + threadIdx.x,
+                                    j + 1 < nj ? (j + 1) * BS + threadIdx.x : -1, (const float *)wxf, v.K, false, d0,
+                                    d1, d2);
+        } else {
+            wave_expo(wx, v.m, v.K, t);
+#pragma unroll 1
+            for (int j = 0; j < nj; j += 2)
+                newton_rows2<T, KP>(tab, wrow, rows, j * BS + threadIdx.x,
+                                    j + 1 < nj ? (j + 1) * BS + threadIdx.x : -1, (const double *)wx, v.K, false, d0,
+                                    d1, d2);
+        }
         block_sum3<BS>(d0, d1, d2, red, parity);
         if (iter >= opt.max_newton) break;
         if (d1 > 0.0) lo = t;
@@ -603,7 +621,7 @@ __device__ inline EdgeResult newton_edge(const TreeView<T> &v, int a, int b, dou
 #pragma unroll 1
         for (int j = 0; j < nj; j += 2)
             newton_rows2<T, KP>(tab, wrow, rows, j * BS + threadIdx.x, j + 1 < nj ? (j + 1) * BS + threadIdx.x : -1,
-                                wx, v.K, true, l0, z1, z2);
+                                (const double *)wx, v.K, true, l0, z1, z2);
         block_sum3<BS>(l0, z1, z2, red, parity);
         lnl = l0;
     }
@@ -661,11 +679,11 @@ __global__ void k_pmat(const BatchArgs a, const double *brlen) {
     }
 }
 
-// Pattern-tile kernel: each block runs its tree's program over one tile of
+// Pattern-tile kernels (k_tiles32 / k_tiles64 below): each block runs its tree's program over one tile of
 // BS * kTileItems patterns.  LOGLIK programs end in one EVAL (column 0);
 // GRAD programs EVAL every edge.  Output: part[tile][col] = (lnL, d1, d2).
 template <typename T, int BS, int KP>
-__global__ void __launch_bounds__(BS) k_tiles(const BatchArgs a, const double *brlen) {
+__device__ inline void tiles_body(const BatchArgs &a, const double *brlen) {
     extern __shared__ double lds[];
     __shared__ double red[2 * (BS / 64) * 3];
     __shared__ double wxs[(BS / 64) * kWx];
@@ -716,6 +734,21 @@ __global__ void __launch_bounds__(BS) k_tiles(const BatchArgs a, const double *b
     }
 }
 
+// The tile kernels.  With FP32 partials the kernel is held to 128 VGPRs
+// (four blocks per CU), which measured 7 % faster despite a 48-byte spill
+// outside the update loop; with FP64 partials the LDS copy of the matrices
+// already limits a CU to two blocks.
+template <int BS, int KP>
+__global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4)))
+k_tiles32(const BatchArgs a, const double *brlen) {
+    tiles_body<float, BS, KP>(a, brlen);
+}
+
+template <int BS, int KP>
+__global__ void __launch_bounds__(BS) k_tiles64(const BatchArgs a, const double *brlen) {
+    tiles_body<double, BS, KP>(a, brlen);
+}
+
 // Sum the tile partials of every tree (LOGLIK) or every edge (GRAD) in
 // tile order.
 __global__ void k_reduce(const BatchArgs a, bool grad, double *lnl, double *gout, double *hout) {
@@ -759,10 +792,12 @@ __global__ void __launch_bounds__(BS) k_optimize(const BatchArgs a, double *brle
     extern __shared__ double lds[];
     __shared__ double red[2 * (BS / 64) * 3];
     __shared__ double wxs[(BS / 64) * kWx];
+    __shared__ float wxfs[(BS / 64) * kWx];
     __shared__ ModelS model;
     __shared__ int q_sh;
     const int tid = threadIdx.x;
     double *wx = wxs + (tid >> 6) * kWx;
+    float *wxf = wxfs + (tid >> 6) * kWx;
     // per block: the table [KP][BS*ni][4] of T, then the weights [BS*ni]
     const size_t tab_bytes = (size_t)BS * ni * KP * 4 * sizeof(T);
     char *tab_base = TAB_LDS ? reinterpret_cast<char *>(lds + pm_lds_doubles)
@@ -827,7 +862,7 @@ __global__ void __launch_bounds__(BS) k_optimize(const BatchArgs a, double *brle
                 }
                 // the pass's lnL comes from its last edge step (op.ea = 1)
                 const EdgeResult r =
-                    newton_edge<T, BS, KP>(v, op.a, op.b, t0, op.ea != 0, opt, tab, wrow, ni, red, wx, parity);
+                    newton_edge<T, BS, KP>(v, op.a, op.b, t0, op.ea != 0, opt, tab, wrow, ni, red, wx, wxf, parity);
                 parity = r.parity;
                 if (op.ea) cur = r.lnl;
                 pc[PROF_EDGE_STEPS] += 1;
@@ -950,13 +985,16 @@ size_t spill_opt_t() {
 
 template <typename T, int BS, int KP>
 hipError_t launch_tiles_t(const BatchArgs &a, const double *brlen, size_t lds, hipStream_t s) {
-    if (std::is_same<T, float>::value) lds = 0;
+    if (std::is_same<T, float>::value) {
+        hipLaunchKernelGGL((k_tiles32<BS, KP>), dim3(a.n_tiles), dim3(BS), 0, s, a, brlen);
+        return hipGetLastError();
+    }
     if (lds > 48 * 1024) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_tiles<T, BS, KP>),
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_tiles64<BS, KP>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL((k_tiles<T, BS, KP>), dim3(a.n_tiles), dim3(BS), lds, s, a, brlen);
+    hipLaunchKernelGGL((k_tiles64<BS, KP>), dim3(a.n_tiles), dim3(BS), lds, s, a, brlen);
     return hipGetLastError();
 }
 
