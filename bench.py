@@ -9,9 +9,10 @@ topology's lnL is within 1e-4 of the FP64 CPU oracle's optimum (stored in
 tests/golden/c2_hillclimb.json by a script that calls only the oracle).
 
 Prints one JSON line.  Extra fields: the same batch in FP64, the plain
-per-topology GPU path (one tree per call, no graph), the pattern-tile
-pruning kernel on a 512-topology batch over four uneven alignments, the
-roofline of the dominant kernel and the oracle timed on this host's cores.
+per-topology GPU path (one tree per call, no graph), the 512-topology batch
+over four uneven alignments (optimised in one launch, and its pruning pass),
+the all-edge gradient of 256 50-taxon trees, the roofline of the dominant
+kernel and the oracle timed on this host's cores.
 """
 import argparse
 import hashlib
@@ -75,6 +76,18 @@ def c3_inputs():
             lens.append(tb)
             idx.append(i)
     return alns, trees, np.concatenate(lens), np.array(idx, np.int32)
+
+
+def c4_inputs():
+    """256 NNI-walk topologies of a 50-taxon x 1500-site GTR+G4 alignment with
+    Exp(mean 0.05) lengths (the gradient workload)."""
+    import synth
+    rng = np.random.default_rng(4)
+    e, b = synth.yule_tree(50, rng, mean=0.05)
+    aln = synth.make_alignment(e, b, 50, 1500, rng, alpha=0.5, n_cats=4)
+    tops = [x for x, _ in synth.nni_bfs(e, b, 50, 256)]
+    lens = rng.exponential(0.05, size=(256, 97))
+    return aln, tops, lens
 
 
 def main():
@@ -266,6 +279,33 @@ def main():
                               "passes_mean": float(po.float().mean()),
                               "achieved_GBs": round(by3o / (ms3o / 1e3) / 1e9, 1)}
         plan3o.close()
+        log("gradient of 256 trees ...")
+        aln4, tops4, lens4 = c4_inputs()
+        A4 = pt.Alignment.from_synth(ctx, aln4)
+        T4 = pt.Trees(tops4)
+        plan4 = pt.Plan(ctx, [A4], T4, pt.PT_PLAN_GRAD, pt.PT_FP32)
+        b4 = torch.tensor(lens4.ravel(), dtype=torch.float64, device=dev)
+        l4 = torch.zeros(T4.n_trees, dtype=torch.float64, device=dev)
+        g4 = torch.zeros_like(b4)
+        with torch.cuda.stream(stream):
+            plan4.set_graphs(True)
+            for _ in range(3):
+                plan4.grad(b4, l4, g4, stream=stream)
+            g0, g1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            g0.record(stream)
+            for _ in range(10):
+                plan4.grad(b4, l4, g4, stream=stream)
+            g1.record(stream)
+            torch.cuda.synchronize()
+        ms4 = g0.elapsed_time(g1) / 10
+        by4 = plan4.traffic(pt.PT_PLAN_GRAD)
+        out["gradient"] = {"workload": "all 97 branch-length gradients of 256 topologies, 50 taxa x 1500 sites "
+                                       "GTR+G4, FP32 partials (adjoint: lower and upper partials, one edge "
+                                       "derivative per edge)",
+                           "ms_per_call": round(ms4, 4), "trees_per_s": round(T4.n_trees / (ms4 / 1e3), 1),
+                           "algorithmic_bytes": by4, "achieved_GBs": round(by4 / (ms4 / 1e3) / 1e9, 1),
+                           "frac_of_peak": round(by4 / (ms4 / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
+        plan4.close()
         out["pruning"] = {"workload": "512 topologies over 27x1949, 36x1812, 50x1133, 64x1008 GTR+G4, FP32",
                           "ms_per_call": round(ms3, 4), "algorithmic_bytes": by3,
                           "achieved_GBs": round(by3 / (ms3 / 1e3) / 1e9, 1),
