@@ -1,0 +1,97 @@
+"""CPU tests of the threshold search's host logic.
+
+The search (FIFO todo queue, visited and good tables keyed by the library's
+host topology keys, NNI proposals, final filter by the last lmax + T) runs
+with its batch optimiser replaced by the FP64 oracle, so no GPU is needed.
+On 6 taxa, with full proposal optimisation from the global maximum, the good
+set must be the NNI-connected component of the superlevel set that contains
+the start (Methods, "Phylogenetic Topographer"); radius 0 must give a subset.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import core as oc
+from oracle import topo
+from paper_1811_11007_amd import search as S
+
+
+class OracleSearch(S.ThresholdSearch):
+    """The search with each batch optimised tree by tree by the oracle."""
+
+    def __init__(self, data, n, **kw):
+        class _Aln:
+            n_taxa = n
+        super().__init__(None, _Aln(), opt=object(), **kw)
+        self.data = data
+        self.batches_seen = []
+
+    def _optimize(self, edge_lists, brlen, masks=None, warm_rows=None):
+        assert warm_rows is None
+        E = 2 * self.n - 3
+        lnl, out, ps = [], np.array(brlen, dtype=np.float64), []
+        for i, e in enumerate(edge_lists):
+            m = None if masks is None else masks[i]
+            l, b, p, _ = oc.optimize(self.data, e, out[i * E:(i + 1) * E], mask=m)
+            out[i * E:(i + 1) * E] = b
+            lnl.append(l)
+            ps.append(p)
+        self.batches_seen.append(len(edge_lists))
+        return np.array(lnl), out, np.array(ps, np.int32)
+
+
+def brute_force(seed, n=6, sites=150):
+    rng = np.random.default_rng(seed)
+    e, b = synth.yule_tree(n, rng, mean=0.15)
+    aln = synth.make_alignment(e, b, n, sites, rng, alpha=0.5, n_cats=4)
+    D = oc.Data.from_alignment(aln)
+    tops = topo.all_topologies(n)
+    E = 2 * n - 3
+    srng = np.random.default_rng(1000 + seed)
+    starts = [np.full(E, 0.1)] + [np.exp(srng.normal(-2.5, 1.5, E)) for _ in range(5)]
+    opt = np.array([[oc.optimize(D, t, s0)[0] for s0 in starts] for t in tops])
+    return D, tops, opt.max(axis=1), opt.min(axis=1)
+
+
+@pytest.mark.parametrize("seed", [72])
+def test_search_logic_against_brute_force(seed):
+    n = 6
+    D, tops, lnl, low = brute_force(seed, n)
+    keys = [topo.key(t, n) for t in tops]
+    by_key = dict(zip(keys, tops))
+    best = int(np.argmax(lnl))
+    lmax = lnl[best]
+    T = -20.0
+    cut = lmax + T
+    assert min(np.min(np.abs(lnl - cut)), np.min(np.abs(low - cut))) > 1e-3
+    assert not np.any((low < cut) & (lnl >= cut))
+    members = {k for k, l in zip(keys, lnl) if l >= cut}
+    comp = {keys[best]}
+    todo = [keys[best]]
+    while todo:
+        k = todo.pop()
+        for ne, _ in topo.nni_neighbors(by_key[k], np.full(2 * n - 3, 0.1), n):
+            kk = topo.key(ne, n)
+            if kk in members and kk not in comp:
+                comp.add(kk)
+                todo.append(kk)
+    start = [(tops[best], np.full(2 * n - 3, 0.1))]
+    s = OracleSearch(D, n, threshold=T, radius=-1, batch=16)
+    res = s.run(start)
+    got = {topo.key(v[1], n) for v in res.good.values()}
+    assert got == comp
+    assert abs(res.lmax - lmax) < 1e-9 * abs(lmax)
+    # batches of at most 16 trees; every good topology was visited
+    assert max(s.batches_seen) <= 16
+    assert res.visited >= len(res.good)
+    s0 = OracleSearch(D, n, threshold=T, radius=0, batch=16)
+    res0 = s0.run(start)
+    got0 = {topo.key(v[1], n) for v in res0.good.values()}
+    assert got0 <= comp and keys[best] in got0
+
+
+def test_search_rejects_bad_settings():
+    with pytest.raises(ValueError):
+        OracleSearch(None, 6, threshold=1.0)
+    with pytest.raises(ValueError):
+        OracleSearch(None, 6, threshold=-1.0, radius=2)
