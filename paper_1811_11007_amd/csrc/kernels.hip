@@ -43,10 +43,6 @@ struct Store<float> {
     __device__ static inline void widen(const Raw &v, double x[4]) {
         x[0] = v.x; x[1] = v.y; x[2] = v.z; x[3] = v.w;
     }
-    __device__ static inline void load(const float *p, double x[4]) {
-        float4 v = *reinterpret_cast<const float4 *>(p);
-        x[0] = v.x; x[1] = v.y; x[2] = v.z; x[3] = v.w;
-    }
     __device__ static inline void store(float *p, const double x[4]) {
         *reinterpret_cast<float4 *>(p) =
             make_float4((float)x[0], (float)x[1], (float)x[2], (float)x[3]);
@@ -67,11 +63,6 @@ struct Store<double> {
     }
     __device__ static inline void widen(const Raw &v, double x[4]) {
         x[0] = v.a.x; x[1] = v.a.y; x[2] = v.b.x; x[3] = v.b.y;
-    }
-    __device__ static inline void load(const double *p, double x[4]) {
-        double2 a = reinterpret_cast<const double2 *>(p)[0];
-        double2 b = reinterpret_cast<const double2 *>(p)[1];
-        x[0] = a.x; x[1] = a.y; x[2] = b.x; x[3] = b.y;
     }
     __device__ static inline void store(double *p, const double x[4]) {
         reinterpret_cast<double2 *>(p)[0] = make_double2(x[0], x[1]);
