@@ -59,7 +59,7 @@ def lib():
         L.or_edge_derivs.argtypes = common + [c_int, dp, dp, dp]
         L.or_gradient.argtypes = common + [dp, dp, dp]
         L.or_optimize.argtypes = [c_int, ip, dp, up, c_int, up, dp, dp, dp, c_d, c_int,
-                                  c_d, c_d, c_d, c_d, c_d, c_int, c_int,
+                                  c_d, c_d, c_d, c_d, c_d, c_int, c_int, c_d,
                                   dp, ip, ip]
         _lib = L
     return _lib
@@ -178,8 +178,10 @@ def gradient(data: Data, edges, brlen):
 
 def optimize(data: Data, edges, brlen, mask=None, t_min=T_MIN, t_max=T_MAX,
              tol_lnl=TOL_LNL, tol_t=TOL_T, tol_newton=TOL_NEWTON,
-             max_passes=MAX_PASSES, max_newton=MAX_NEWTON):
-    """Coordinate-wise Newton; returns (lnL, lengths, passes, converged)."""
+             max_passes=MAX_PASSES, max_newton=MAX_NEWTON, prior_rate=0.0):
+    """Coordinate-wise Newton; returns (objective, lengths, passes, converged).
+    The objective is lnL, or with prior_rate > 0 lnL plus the log density of
+    an exponential prior of that rate on every length (MAP lengths)."""
     e, b = _tree(edges, brlen)
     b = b.copy()
     m = None
@@ -191,5 +193,5 @@ def optimize(data: Data, edges, brlen, mask=None, t_min=T_MIN, t_max=T_MAX,
     _check(lib().or_optimize(data.n, _i(e), _d(b), _u(m) if m is not None else None,
                              *data.args(), float(t_min), float(t_max), float(tol_lnl),
                              float(tol_t), float(tol_newton), int(max_passes), int(max_newton),
-                             _d(l), _i(ps), _i(cv)))
+                             float(prior_rate), _d(l), _i(ps), _i(cv)))
     return float(l[0]), b, int(ps[0]), bool(cv[0])

@@ -492,7 +492,10 @@ int or_gradient(int n, const int32_t *edges, const double *brlen,
 
 /* ------------------------------------------------------------ optimisation */
 
-/* One edge: safeguarded, projected Newton on t in [t_min, t_max].
+/* One edge: safeguarded, projected Newton on t in [t_min, t_max] for the
+ * objective lnL(t) - prior_rate * t (prior_rate = 0: maximum likelihood; > 0:
+ * the log density of an exponential prior on the length added, so the first
+ * derivative loses prior_rate and the second is unchanged).
  *  - the bracket (lo, hi) starts as [t_min, t_max] and shrinks to t from
  *    the side the first derivative points away from;
  *  - a Newton step is taken when d2 < 0 and the step stays in the bracket
@@ -501,7 +504,7 @@ int or_gradient(int n, const int32_t *edges, const double *brlen,
  *  - a bound with the derivative pointing outwards is an optimum;
  *  - stop when the step is at most tol * max(t, 1e-6). */
 static double newton_edge(const data_t *d, const sides_t *s, double t0, double t_min, double t_max,
-                          double tol, int max_iter, int *iters)
+                          double tol, int max_iter, double prior_rate, int *iters)
 {
     double lo = t_min, hi = t_max;
     double t = t0 < t_min ? t_min : (t0 > t_max ? t_max : t0);
@@ -509,6 +512,7 @@ static double newton_edge(const data_t *d, const sides_t *s, double t0, double t
     for (; it < max_iter; ++it) {
         double d1, d2;
         edge_eval(d, s->A, s->cA, s->B, s->cB, t, NULL, &d1, &d2);
+        d1 -= prior_rate;
         if (d1 > 0.0) lo = t;
         else if (d1 < 0.0) hi = t;
         else break;
@@ -527,22 +531,36 @@ static double newton_edge(const data_t *d, const sides_t *s, double t0, double t
     return t;
 }
 
+/* Log density of independent exponential priors of rate `rate` on every
+ * length, sum over e of log(rate) - rate * t_e (0 when rate is 0). */
+static double log_prior(int n_edges, const double *brlen, double rate)
+{
+    if (!(rate > 0.0)) return 0.0;
+    double s = 0.0;
+    for (int e = 0; e < n_edges; ++e) s += log(rate) - rate * brlen[e];
+    return s;
+}
+
 /* Coordinate-wise Newton over the masked edges (ascending edge index) until
- * a pass raises lnL by less than tol_lnl and moves no edge by more than
- * tol_t relative, or max_passes passes.  Returns the final lnL, the number
- * of passes and whether the stopping rule was met (1) or not (0). */
+ * a pass raises the objective by less than tol_lnl and moves no edge by more
+ * than tol_t relative, or max_passes passes.  The objective is lnL, plus with
+ * prior_rate > 0 the log density of an exponential branch-length prior of
+ * that rate on every edge (MAP lengths; Methods, "Phylogenetic Topographer",
+ * the optional branch-length prior).  Returns the final objective, the
+ * number of passes and whether the stopping rule was met (1) or not (0). */
 int or_optimize(int n, const int32_t *edges, double *brlen, const uint8_t *mask,
                 int P, const uint8_t *tips, const double *w,
                 const double *rates, const double *freqs, double alpha, int K,
                 double t_min, double t_max, double tol_lnl, double tol_t,
-                double tol_newton, int max_passes, int max_newton,
+                double tol_newton, int max_passes, int max_newton, double prior_rate,
                 double *lnl_out, int *passes_out, int *converged_out)
 {
     tree_t t; data_t d;
     int rc = tree_build(n, edges, &t);
     if (rc) return rc;
     if ((rc = data_init(&d, n, P, tips, w, rates, freqs, alpha, K, 1)) ||
-        (rc = check_lengths(t.n_edges, brlen)) || !(t_min > 0.0) || !(t_max > t_min)) {
+        (rc = check_lengths(t.n_edges, brlen)) || !(t_min > 0.0) || !(t_max > t_min) ||
+        !(prior_rate >= 0.0) || !isfinite(prior_rate)) {
         tree_free(&t); return rc ? rc : -1;
     }
     sides_t s;
@@ -560,7 +578,7 @@ int or_optimize(int n, const int32_t *edges, double *brlen, const uint8_t *mask,
             rc = edge_sides(&t, &d, brlen, edges, e, &s);
             if (rc) break;
             double old = brlen[e];
-            brlen[e] = newton_edge(&d, &s, old, t_min, t_max, tol_newton, max_newton, NULL);
+            brlen[e] = newton_edge(&d, &s, old, t_min, t_max, tol_newton, max_newton, prior_rate, NULL);
             double rel = fabs(brlen[e] - old) / fmax(old, 1e-6);
             if (rel > max_rel) max_rel = rel;
         }
@@ -569,6 +587,7 @@ int or_optimize(int n, const int32_t *edges, double *brlen, const uint8_t *mask,
         rc = edge_sides(&t, &d, brlen, edges, 0, &s);
         if (rc) break;
         edge_eval(&d, s.A, s.cA, s.B, s.cB, brlen[0], &cur, NULL, NULL);
+        cur += log_prior(t.n_edges, brlen, prior_rate);
         if (cur - prev < tol_lnl && max_rel < tol_t) { conv = 1; break; }
         prev = cur;
     }

@@ -11,6 +11,10 @@
   with c and b with d (Methods, "Phylogenetic Topographer"; 2(n-3) per tree).
 * Enumeration: all (2n-5)!! unrooted binary topologies by stepwise
   addition of taxa onto every edge.
+* Radius masks: the edges within radius r of a new edge, measured from one
+  of its endpoints (Methods, "Phylogenetic Topographer", the radius option;
+  r = 0 is the new edge alone, r = 1 adds two neighbouring edges, r = -1 is
+  every edge).
 """
 from __future__ import annotations
 
@@ -92,6 +96,37 @@ def nni_touched(edges, n):
         ev = [x for (_, x) in adj[v] if x != e]
         for k, ec in enumerate(ev):
             out.append((e, eu[1], ec, eu[0], ev[1 - k]))
+    return out
+
+
+def radius_edges(edges, n, centre, r):
+    """The set of edges a radius-r proposal optimises.  The selected node u
+    is the first endpoint of the centre edge that is an internal node (the
+    paper leaves the choice open).  With the centre edge cut out, an edge
+    (x, y) on u's side lies at depth 1 + min(dist(u, x), dist(u, y)) and the
+    centre edge at depth 0; the edges of depth <= r are optimised."""
+    edges = np.asarray(edges).tolist()
+    E = len(edges)
+    if r == -1:
+        return set(range(E))
+    u = edges[centre][0] if edges[centre][0] >= n else edges[centre][1]
+    if u < n:
+        return {centre}
+    adj = _adj(edges, n)
+    dist = {u: 0}
+    frontier = [u]
+    while frontier:  # breadth-first distances without the centre edge
+        nxt = []
+        for x in frontier:
+            for y, e in adj[x]:
+                if e != centre and y not in dist:
+                    dist[y] = dist[x] + 1
+                    nxt.append(y)
+        frontier = nxt
+    out = {centre}
+    for e, (x, y) in enumerate(edges):
+        if e != centre and x in dist and y in dist and 1 + min(dist[x], dist[y]) <= r:
+            out.add(e)
     return out
 
 

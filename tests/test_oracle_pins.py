@@ -9,6 +9,8 @@ import math
 import numpy as np
 import pytest
 from scipy.linalg import expm
+from scipy.optimize import brentq
+from scipy.sparse.csgraph import shortest_path
 from scipy.special import gammainc, gammaincinv
 
 import synth
@@ -370,6 +372,65 @@ def test_optimum_vs_golden_section():
     assert np.max(np.abs(b - bg) / np.maximum(b, 1e-3)) < 1e-3
 
 
+# --------------------------------------------- MAP lengths (exponential prior)
+#
+# With an Exponential(rate) prior on every length the optimiser maximises
+# lnL + sum_e (log rate - rate * t_e) (Methods, "Phylogenetic Topographer":
+# the optional branch-length prior; the paper's runs use rate 10).
+
+def jc_two_taxon_dlnl(N, k, t):
+    """d lnL / dt of two JC69 sequences with k mismatches, written out."""
+    x = math.exp(-4.0 * t / 3.0)
+    return -(N - k) * x / (0.25 + 0.75 * x) + k * (x / 3.0) / (0.25 - 0.25 * x)
+
+
+def jc_two_taxon_lnl(N, k, t):
+    x = math.exp(-4.0 * t / 3.0)
+    return N * math.log(0.25) + (N - k) * math.log(0.25 + 0.75 * x) + k * math.log(0.25 - 0.25 * x)
+
+
+@pytest.mark.parametrize("N,k,rate", [(200, 37, 10.0), (1000, 300, 1.0), (100, 80, 10.0), (200, 1, 50.0)])
+def test_two_taxon_map_closed_form(N, k, rate):
+    """The MAP length solves d lnL / dt = rate; brentq on the written-out
+    derivative finds it independently.  With k/N >= 3/4 the ML length is
+    unbounded but the MAP length is finite."""
+    t_star = brentq(lambda t: jc_two_taxon_dlnl(N, k, t) - rate, 1e-9, 50.0, xtol=1e-15, rtol=1e-15)
+    obj_star = jc_two_taxon_lnl(N, k, t_star) + math.log(rate) - rate * t_star
+    for start in (1e-4, 0.1, 5.0):
+        l, b, _, conv = oc.optimize(two_taxon_data(N, k), [[0, 1]], [start], prior_rate=rate)
+        assert conv
+        assert abs(b[0] - t_star) < 1e-9 * max(1.0, t_star)
+        assert abs(l - obj_star) < 1e-9 * abs(obj_star)
+
+
+def test_two_taxon_map_lower_bound():
+    # no mismatches: lnL falls with t, so the prior keeps t at the lower bound
+    l, b, _, _ = oc.optimize(two_taxon_data(100, 0), [[0, 1]], [0.3], prior_rate=10.0)
+    assert abs(b[0] - oc.T_MIN) < 1e-15
+    assert abs(l - (jc_two_taxon_lnl(100, 0, oc.T_MIN) + math.log(10.0) - 10.0 * oc.T_MIN)) < 1e-9
+
+
+@pytest.mark.parametrize("n,seed,rate", [(5, 25, 10.0), (8, 26, 3.0)])
+def test_map_optimum_kkt(n, seed, rate):
+    edges, brlen, aln = small_case(n, seed, sites=300, mean=0.1)
+    D = oc.Data.from_alignment(aln)
+    obj, b, _, conv = oc.optimize(D, edges, brlen, prior_rate=rate)
+    assert conv
+    assert obj == pytest.approx(oc.loglik(D, edges, b) + len(b) * math.log(rate) - rate * b.sum(), abs=1e-9)
+    for e in range(len(b)):
+        _, d1, d2 = oc.edge_derivs(D, edges, b, e)
+        if b[e] <= oc.T_MIN:
+            assert d1 - rate <= 1e-6
+        else:
+            assert abs(d1 - rate) <= 1e-5
+            assert d2 < 0
+    # the prior shortens the tree, and a vanishing rate gives the ML lengths
+    _, bm, _, _ = oc.optimize(D, edges, brlen)
+    assert b.sum() < bm.sum()
+    _, b0, _, _ = oc.optimize(D, edges, brlen, prior_rate=1e-12)
+    assert np.max(np.abs(b0 - bm)) < 1e-7
+
+
 def test_mask_only_moves_masked_edges():
     edges, brlen, aln = small_case(7, 24, sites=200)
     D = oc.Data.from_alignment(aln)
@@ -451,3 +512,50 @@ def test_nni_graph_n5():
         seen.add(k)
         stack += [topo.key(e, 5) for e, _ in topo.nni_neighbors(keys[k], np.ones(7), 5)]
     assert len(seen) == 15
+
+
+# ---------------------------------------------------------- radius masks
+#
+# A 6-taxon caterpillar written out by hand: leaves 0..5, internal 6..9.
+CATERPILLAR = [(0, 6), (1, 6), (6, 7), (2, 7), (7, 8), (3, 8), (8, 9), (4, 9), (5, 9)]
+
+
+@pytest.mark.parametrize("centre,r,want", [
+    (4, 0, {4}),                     # radius 0: the new edge alone
+    (4, 1, {4, 2, 3}),               # radius 1: the new edge and two neighbours
+    (4, 2, {4, 2, 3, 0, 1}),
+    (4, 3, {4, 2, 3, 0, 1}),         # u's side holds 3 leaves: 2*3-1 edges
+    (6, 1, {6, 4, 5}),
+    (6, 2, {6, 4, 5, 2, 3}),
+    (6, 3, {6, 4, 5, 2, 3, 0, 1}),
+    (2, 1, {2, 0, 1}),
+    (0, 1, {0, 1, 2}),               # a pendant edge walks from its internal end
+    (4, -1, set(range(9))),
+])
+def test_radius_edges_by_hand(centre, r, want):
+    assert topo.radius_edges(CATERPILLAR, 6, centre, r) == want
+
+
+@pytest.mark.parametrize("n,seed", [(8, 1), (27, 2)])
+def test_radius_edges_invariants(n, seed):
+    rng = np.random.default_rng(seed)
+    edges, _ = synth.random_tree(n, rng)
+    E = 2 * n - 3
+    A = np.zeros((2 * n - 2, 2 * n - 2))
+    for a, b in edges:
+        A[a, b] = A[b, a] = 1
+    dist = shortest_path(A, unweighted=True)
+    for c in range(E):
+        u = edges[c][0] if edges[c][0] >= n else edges[c][1]
+        sets = [topo.radius_edges(edges, n, c, r) for r in range(2 * n)]
+        assert sets[0] == {c}
+        for a, b in zip(sets, sets[1:]):
+            assert a <= b
+        # radius 1: the centre and the other two edges at u
+        at_u = {e for e in range(E) if u in edges[e]}
+        assert sets[1] == at_u
+        # large radius: the centre plus every edge of the rooted subtree at u,
+        # which has 2L - 2 edges for its L leaves (the leaves nearer u than v)
+        v = edges[c][1] if u == edges[c][0] else edges[c][0]
+        L = int(np.sum(dist[:n, u] < dist[:n, v]))
+        assert len(sets[-1]) == 2 * L - 1
