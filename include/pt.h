@@ -241,6 +241,19 @@ pt_status pt_topology_key(int32_t n, const int32_t *edges, uint64_t *out);
  * out uint64[count][n-3][W].  On error nothing is guaranteed about out. */
 pt_status pt_topology_keys(int32_t n, int32_t count, const int32_t *edges, uint64_t *out);
 
+/* Radius-limited optimisation masks (Methods, "Phylogenetic Topographer":
+ * proposals may optimise the lengths within radius r of the new edge).  For
+ * tree i, centres[i] is the new edge and u its first endpoint that is an
+ * internal node.  The centre edge has depth 0; walking away from the centre
+ * edge through u, each edge is one deeper than the edge it is reached from.
+ * out[i][e] = 1 for the edges of depth <= radius, else 0: radius 0 is the
+ * centre edge alone, radius 1 adds u's two other edges, and radius -1 marks
+ * every edge.  edges int32[count][2n-3][2], centres int32[count], out
+ * uint8[count][2n-3] (the opt_mask layout).  EINVAL for an invalid tree, a
+ * centre out of range or radius < -1; out is then undefined. */
+pt_status pt_radius_masks(int32_t n, int32_t count, const int32_t *edges, const int32_t *centres,
+                          int32_t radius, uint8_t *out);
+
 /* -------------------------------------------- warm-start network (learned) */
 
 /* Features of every NNI move of a tree whose lengths have been optimised,

@@ -25,7 +25,7 @@ EXPORTS = [
     "pt_plan_create", "pt_plan_destroy", "pt_plan_set_graphs", "pt_plan_loglik",
     "pt_plan_optimize", "pt_plan_grad", "pt_plan_autotune", "pt_plan_traffic", "pt_plan_set_profile", "pt_plan_info",
     "pt_model_info", "pt_tree_check", "pt_nni_neighbors", "pt_topology_key", "pt_topology_keys",
-    "pt_nni_features",
+    "pt_nni_features", "pt_radius_masks",
     "pt_mlp_create", "pt_mlp_destroy", "pt_mlp_param_count", "pt_mlp_get_params", "pt_mlp_set_params",
     "pt_mlp_forward", "pt_mlp_warm_start", "pt_mlp_gradient", "pt_mlp_train_step",
 ]
@@ -111,6 +111,7 @@ def lib():
         L.pt_topology_key.argtypes = [i32, vp, vp]
         L.pt_topology_keys.argtypes = [i32, i32, vp, vp]
         L.pt_nni_features.argtypes = [i32, vp, vp, vp]
+        L.pt_radius_masks.argtypes = [i32, i32, vp, vp, i32, vp]
         L.pt_mlp_create.argtypes = [vp, i32, i32, i32, vp, P(vp)]
         L.pt_mlp_destroy.argtypes = [vp]
         L.pt_mlp_destroy.restype = None
@@ -317,6 +318,18 @@ def pt_nni_features(n, edges, brlen):
     b = np.ascontiguousarray(brlen, dtype=np.float64)
     out = np.zeros((max(2 * (n - 3), 0), PT_NNI_FEATURES), np.float32)
     check(lib().pt_nni_features(int(n), _ptr(e), _ptr(b), _ptr(out)))
+    return out
+
+
+def pt_radius_masks(n, edges, centres, radius):
+    """uint8[count][2n-3] radius-limited optimisation masks of a stack of
+    trees (edges [count][2n-3][2]) around their centre edges."""
+    e = np.ascontiguousarray(edges, dtype=np.int32)
+    c = np.ascontiguousarray(centres, dtype=np.int32)
+    if e.ndim != 3 or c.shape != (e.shape[0],):
+        raise ValueError("edges must be [count][2n-3][2] and centres [count]")
+    out = np.zeros((e.shape[0], e.shape[1]), np.uint8)
+    check(lib().pt_radius_masks(int(n), int(e.shape[0]), _ptr(e), _ptr(c), int(radius), _ptr(out)))
     return out
 
 

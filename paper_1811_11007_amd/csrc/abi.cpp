@@ -963,6 +963,18 @@ pt_status pt_topology_keys(int32_t n, int32_t count, const int32_t *edges, uint6
     return PT_OK;
 }
 
+pt_status pt_radius_masks(int32_t n, int32_t count, const int32_t *edges, const int32_t *centres, int32_t radius,
+                          uint8_t *out) {
+    if (count < 0 || (count > 0 && (!edges || !centres || !out))) return fail(PT_EINVAL, "bad arguments");
+    const size_t E = n >= 2 ? (size_t)(n == 2 ? 1 : 2 * n - 3) : 0;
+    std::string err;
+    for (int32_t i = 0; i < count; ++i) {
+        pt_status st = pt::radius_mask(n, edges + i * E * 2, centres[i], radius, out + i * E, err);
+        if (st) return fail(st, "tree " + std::to_string(i) + ": " + err);
+    }
+    return PT_OK;
+}
+
 pt_status pt_nni_features(int32_t n, const int32_t *edges, const double *brlen, float *out) {
     if (!edges || !brlen || !out) return fail(PT_EINVAL, "NULL argument");
     std::string err;

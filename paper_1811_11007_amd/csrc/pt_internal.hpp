@@ -47,5 +47,6 @@ pt_status nni_neighbors(int n, const int32_t *edges, const double *brlen, int32_
                         double *out_brlen, int32_t *out_touched, std::string &err);
 pt_status topology_key(int n, const int32_t *edges, uint64_t *out, std::string &err);
 pt_status nni_features(int n, const int32_t *edges, const double *brlen, float *out, std::string &err);
+pt_status radius_mask(int n, const int32_t *edges, int centre, int r, uint8_t *out, std::string &err);
 
 }  // namespace pt

@@ -267,6 +267,46 @@ pt_status nni_neighbors(int n, const int32_t *edges, const double *brlen, int32_
     return PT_OK;
 }
 
+// Radius-limited optimisation mask (Methods, "Phylogenetic Topographer",
+// the radius option): the centre edge has depth 0; from the selected
+// endpoint u of the centre edge (its first endpoint that is an internal
+// node), each further edge reached through u is one deeper than the edge it
+// is reached from.  Edges of depth <= r are marked; r = -1 marks all.  The
+// walk never crosses the centre edge, so r = 1 gives the centre edge and
+// u's two other edges.
+pt_status radius_mask(int n, const int32_t *edges, int centre, int r, uint8_t *out, std::string &err) {
+    Tree t;
+    pt_status st = build_tree(n, edges, t, err);
+    if (st) return st;
+    const int E = t.n_edges;
+    if (centre < 0 || centre >= E) { err = "centre edge out of range"; return PT_EINVAL; }
+    if (r < -1) { err = "radius must be >= -1"; return PT_EINVAL; }
+    if (r == -1) {
+        std::fill(out, out + E, (uint8_t)1);
+        return PT_OK;
+    }
+    std::fill(out, out + E, (uint8_t)0);
+    out[centre] = 1;
+    int u = edges[2 * centre];
+    if (u < n) u = edges[2 * centre + 1];
+    if (u < n || r == 0) return PT_OK;
+    // frontier of (node, edge it was entered by, depth of that edge)
+    struct Item { int node, via, depth; };
+    std::vector<Item> todo{{u, centre, 0}};
+    while (!todo.empty()) {
+        const Item it = todo.back();
+        todo.pop_back();
+        if (it.node < n || it.depth == r) continue;
+        for (int j = 0; j < 3; ++j) {
+            const int f = t.nedge[3 * it.node + j];
+            if (f == it.via) continue;
+            out[f] = 1;
+            todo.push_back({t.nbr[3 * it.node + j], f, it.depth + 1});
+        }
+    }
+    return PT_OK;
+}
+
 namespace {
 
 // Leaf count and total edge length of the subtree hanging from `node` away

@@ -5,10 +5,12 @@ Topographer"): a FIFO todo queue of candidate topologies, a visited table of
 every topology whose branch lengths were fully optimised, and a good table
 of those whose optimised lnL is at least lmax + T (T < 0).  Visiting a
 topology optimises all its lengths; a good topology proposes each of its
-unvisited NNI neighbours, whose lengths are partially optimised (radius 0:
-the new edge only; radius -1: all edges) and which join the queue when that
-partial lnL is at least lmax + T.  Every judgement of a topology as good
-uses its fully optimised lnL.
+unvisited NNI neighbours, whose lengths are partially optimised and which
+join the queue when that partial lnL is at least lmax + T.  Every judgement
+of a topology as good uses its fully optimised lnL.  A proposal's partial
+optimisation covers the lengths within its radius r of the new edge
+(pt_radius_masks: r = 0 the new edge only, r = 1 adds two neighbouring
+edges, and so on; r = -1 all edges).
 
 Batching: the queue is consumed a batch at a time, so one batch of visits
 and one batch of proposals are each a single persistent launch of the
@@ -73,9 +75,9 @@ class ThresholdSearch:
                  precision=L.PT_FP32, batch=1024, opt=None):
         if threshold >= 0:
             raise ValueError("the threshold offset T must be negative")
-        if radius not in (0, -1):
-            raise ValueError("radius must be 0 (new edge only) or -1 (all edges)")
-        self.ctx, self.aln, self.T, self.radius, self.warm = ctx, aln, float(threshold), radius, warm
+        if int(radius) != radius or radius < -1:
+            raise ValueError("radius must be an integer >= 0, or -1 for all edges")
+        self.ctx, self.aln, self.T, self.radius, self.warm = ctx, aln, float(threshold), int(radius), warm
         self.precision, self.batch = precision, int(batch)
         self.opt = opt if opt is not None else L.opt_default(precision)
         self.n = aln.n_taxa
@@ -183,10 +185,8 @@ class ThresholdSearch:
                 trees = [p[1] for p in chunk]
                 starts = np.concatenate([p[2] for p in chunk])
                 masks = None
-                if radius == 0:
-                    m = np.zeros((nc, E), np.uint8)
-                    m[np.arange(nc), [p[4][0] for p in chunk]] = 1
-                    masks = list(m)
+                if radius >= 0:
+                    masks = list(L.pt_radius_masks(n, np.stack(trees), [p[4][0] for p in chunk], radius))
                 warm_rows = None
                 if dual:
                     X = np.stack([p[3] for p in chunk]).astype(np.float32)
@@ -220,3 +220,55 @@ class ThresholdSearch:
                             queued=stats["queued"], full_passes=stats["full_passes"],
                             full_time_s=stats["full_time"], proposal_time_s=stats["prop_time"],
                             batches=stats["batches"], warm_better=stats["warm_better"], samples=samples)
+
+
+def main():
+    """Threshold searches at several proposal radii on one synthetic workload,
+    one JSON line per radius: good, visited and proposed counts, time, and
+    the good topologies that the radius -1 search found and this one missed.
+
+      python -m paper_1811_11007_amd.search --seed 6 --radii -1 0 1 2
+    """
+    import argparse
+    import json
+    import sys
+
+    from .train_warmstart import optimise_start, workload
+
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--seed", type=int, default=6)
+    ap.add_argument("--threshold", type=float, default=-10.0)
+    ap.add_argument("--radii", type=int, nargs="+", default=[-1, 0, 1, 2])
+    ap.add_argument("--batch", type=int, default=1024)
+    ap.add_argument("--warm", default=None, help="warm-start network weights (JSON)")
+    args = ap.parse_args()
+
+    def log(*a):
+        print(*a, file=sys.stderr, flush=True)
+
+    ctx = L.Context(0)
+    e, b, aln = workload(args.seed)
+    A = L.Alignment.from_synth(ctx, aln)
+    b0, l0 = optimise_start(ctx, A, e, b)
+    log("seed %d: %d taxa, %d patterns, start lnL %.4f" % (args.seed, aln.n_taxa, aln.n_patterns, l0))
+    warm = WarmStart.load(ctx, args.warm) if args.warm else None
+    full = None
+    for r in args.radii:
+        t0 = time.perf_counter()
+        res = ThresholdSearch(ctx, A, threshold=args.threshold, radius=r, warm=warm, batch=args.batch).run(
+            [(e, b0)], progress=log)
+        secs = time.perf_counter() - t0
+        good = set(res.good)
+        if r == -1 and full is None:
+            full = good
+        print(json.dumps({
+            "seed": args.seed, "radius": r, "threshold": args.threshold, "warm": bool(warm),
+            "good": len(good), "visited": res.visited, "proposed": res.proposed, "lmax": round(res.lmax, 4),
+            "seconds": round(secs, 2), "proposal_seconds": round(res.proposal_time_s, 2),
+            "missed": None if full is None else len(full - good),
+            "extra": None if full is None else len(good - full)}), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -213,24 +213,30 @@ def test_arena_cap_splits_batches_identically(ctx, monkeypatch):
     assert ei.value.code == -2
 
 
-def test_masked_optimisation_radius0(ctx):
-    """Only the new edge of each NNI neighbour moves (the paper's default
-    proposal step); compared with the oracle under the same mask."""
+@pytest.mark.parametrize("radius", [0, 1, 2])
+def test_masked_optimisation_radius(ctx, radius):
+    """Radius-limited proposal optimisation (radius 0, the paper's default:
+    only the new edge of each NNI neighbour moves); the library's masks and
+    optimum are compared with the oracle's own radius sets and optimum."""
     rng = np.random.default_rng(43)
     e, b = synth.yule_tree(12, rng, mean=0.08)
     aln = synth.make_alignment(e, b, 12, 500, rng, alpha=0.5, n_cats=4)
     A = pt.Alignment.from_synth(ctx, aln)
     ne, nb, touched = pt.pt_nni_neighbors(12, e, b)
     T = pt.Trees(list(ne))
-    mask = np.zeros((len(ne), 21), np.uint8)
-    mask[np.arange(len(ne)), touched[:, 0]] = 1
+    mask = pt.pt_radius_masks(12, ne, touched[:, 0], radius)
+    D = oc.Data.from_alignment(aln)
+    want_mask = np.zeros_like(mask)
+    for i in range(len(ne)):
+        want_mask[i, sorted(topo.radius_edges(ne[i], 12, int(touched[i, 0]), radius))] = 1
+    assert np.array_equal(mask, want_mask)
+    print("radius", radius, "edges per proposal", mask.sum(axis=1).min(), "-", mask.sum(axis=1).max(), flush=True)
     l, bo, _, st = pt.pt_batch_optimize_branches(ctx, [A], T, nb.ravel(), mask=mask.ravel(), precision=pt.PT_FP64)
     bo = bo.reshape(len(ne), 21)
-    D = oc.Data.from_alignment(aln)
     for i in range(len(ne)):
-        keep = mask[i] == 0
+        keep = want_mask[i] == 0
         assert np.array_equal(bo[i][keep], nb[i][keep])
-        want = oc.optimize(D, ne[i], nb[i], mask=mask[i])[0]
+        want = oc.optimize(D, ne[i], nb[i], mask=want_mask[i])[0]
         assert abs(l[i] - want) < 1e-8 * abs(want)
 
 

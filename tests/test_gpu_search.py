@@ -5,8 +5,9 @@ For n = 6 taxa the oracle optimises every one of the 105 unrooted topologies
 maximum as the start, the search's good set must equal the NNI-connected
 component, containing the start, of the superlevel set {T : lnL(T) >= lmax + T}
 (Methods, "Phylogenetic Topographer": every unvisited neighbour of a good
-topology is proposed, and full optimisation judges it exactly).  With radius 0
-(only the new edge optimised when proposing) the good set is a subset of it.
+topology is proposed, and full optimisation judges it exactly).  With radius
+0, 1 or 2 (only the lengths near the new edge optimised when proposing) the
+good set is a subset of it.
 
 Branch-length likelihoods can have several local optima, and which one an
 optimiser reaches depends on its starting lengths.  The oracle therefore
@@ -96,8 +97,9 @@ def test_search_equals_superlevel_component(ctx, seed):
         i = keys.index(k)
         # one of the topology's optima (the search starts from inherited lengths)
         assert low[i] - 1e-6 * abs(l) <= l <= lnl[i] + 1e-6 * abs(l)
-    res0 = ThresholdSearch(ctx, A, threshold=T, radius=0, precision=pt.PT_FP64, batch=64).run(start)
-    got0 = {topo.key(v[1], n) for v in res0.good.values()}
-    say("radius 0 found", len(got0), "of", len(comp))
-    assert got0 <= comp
-    assert keys[best] in got0
+    for radius in (0, 1, 2):
+        res_r = ThresholdSearch(ctx, A, threshold=T, radius=radius, precision=pt.PT_FP64, batch=64).run(start)
+        got_r = {topo.key(v[1], n) for v in res_r.good.values()}
+        say("radius", radius, "found", len(got_r), "of", len(comp))
+        assert got_r <= comp
+        assert keys[best] in got_r

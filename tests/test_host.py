@@ -137,6 +137,39 @@ def test_nni_neighbours_match_oracle(n, seed):
         assert set(ot[i][1:].tolist()) == around
 
 
+@pytest.mark.parametrize("n,seed", [(4, 21), (9, 22), (27, 23), (64, 24)])
+def test_radius_masks_match_oracle(n, seed):
+    rng = np.random.default_rng(seed)
+    edges, brlen = synth.yule_tree(n, rng)
+    oe, _, ot = pt.pt_nni_neighbors(n, edges, brlen)
+    E = 2 * n - 3
+    for r in (-1, 0, 1, 2, 3, 2 * n):
+        got = pt.pt_radius_masks(n, oe, ot[:, 0], r)
+        assert got.shape == (len(oe), E)
+        for i in range(len(oe)):
+            want = topo.radius_edges(oe[i], n, int(ot[i, 0]), r)
+            assert set(np.flatnonzero(got[i]).tolist()) == want
+    # every centre of one tree, including pendant edges
+    stack = np.repeat(np.asarray(edges, np.int32)[None], E, axis=0)
+    got = pt.pt_radius_masks(n, stack, np.arange(E), 2)
+    for c in range(E):
+        assert set(np.flatnonzero(got[c]).tolist()) == topo.radius_edges(edges, n, c, 2)
+
+
+def test_radius_masks_reject_bad_input():
+    edges, _ = synth.yule_tree(6, np.random.default_rng(0))
+    stack = np.asarray(edges, np.int32)[None]
+    for centre, r in ((9, 0), (-1, 0), (0, -2)):
+        with pytest.raises(pt.PTError) as ei:
+            pt.pt_radius_masks(6, stack, [centre], r)
+        assert ei.value.code == -1
+    bad = stack.copy()
+    bad[0, 0] = [0, 0]
+    with pytest.raises(pt.PTError):
+        pt.pt_radius_masks(6, bad, [0], 1)
+    assert pt.pt_radius_masks(6, stack[:0], np.zeros(0, np.int32), 1).shape == (0, 9)
+
+
 def test_enumerated_topologies_have_distinct_keys():
     keys = {key_as_ints(pt.pt_topology_key(7, t), 7) for t in synth.all_topologies(7)}
     assert len(keys) == 945

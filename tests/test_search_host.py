@@ -88,10 +88,16 @@ def test_search_logic_against_brute_force(seed):
     res0 = s0.run(start)
     got0 = {topo.key(v[1], n) for v in res0.good.values()}
     assert got0 <= comp and keys[best] in got0
+    # radius 1 optimises three lengths per proposal: never more than the full component
+    s1 = OracleSearch(D, n, threshold=T, radius=1, batch=16)
+    got1 = {topo.key(v[1], n) for v in s1.run(start).good.values()}
+    assert got1 <= comp and keys[best] in got1
 
 
 def test_search_rejects_bad_settings():
     with pytest.raises(ValueError):
         OracleSearch(None, 6, threshold=1.0)
     with pytest.raises(ValueError):
-        OracleSearch(None, 6, threshold=-1.0, radius=2)
+        OracleSearch(None, 6, threshold=-1.0, radius=-2)
+    with pytest.raises(ValueError):
+        OracleSearch(None, 6, threshold=-1.0, radius=0.5)
