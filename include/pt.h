@@ -102,16 +102,24 @@ typedef struct {
  * when a step would move t by at most tol_newton * max(t, 1e-6) (not taken),
  * or after taking a Newton step of at most sqrt(tol_newton) * max(t, 1e-6)
  * (quadratic convergence leaves an error of order tol_newton).  Per tree:
- * passes over the masked edges until a pass raises lnL by less than tol_lnl
- * and changes no length by more than tol_t relative, or max_passes. */
+ * passes over the masked edges until a pass raises the objective by less
+ * than tol_lnl and changes no length by more than tol_t relative, or
+ * max_passes.
+ * The objective is lnL (prior_rate = 0, maximum likelihood) or, with
+ * prior_rate > 0, lnL plus the log density of independent Exponential
+ * (prior_rate) priors on every length, sum_e (log prior_rate - prior_rate
+ * t_e): MAP lengths (Methods, "Phylogenetic Topographer": the optional
+ * exponential branch-length prior; the paper's runs use rate 10).  The
+ * optimiser's lnl output is then that objective. */
 typedef struct {
     double t_min, t_max;
     double tol_lnl, tol_t, tol_newton;
     int32_t max_passes, max_newton;
+    double prior_rate; /* >= 0, finite */
 } pt_opt;
 
 /* Defaults for a precision: t_min 1e-8, t_max 100, max_passes 200,
- * max_newton 32; FP64 tol_lnl 1e-8, tol_t 1e-5, tol_newton 1e-9; FP32
+ * max_newton 32, prior_rate 0; FP64 tol_lnl 1e-8, tol_t 1e-5, tol_newton 1e-9; FP32
  * tol_lnl 1e-5, tol_t 1e-3, tol_newton 1e-6 (FP32 partials cannot resolve
  * lnL changes much below 1e-5 on alignments of ~1e3 patterns; the reported
  * lnL is evaluated from FP64 partials at the final lengths). */

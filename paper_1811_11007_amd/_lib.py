@@ -58,7 +58,8 @@ class pt_adam(ctypes.Structure):
 class pt_opt(ctypes.Structure):
     _fields_ = [("t_min", ctypes.c_double), ("t_max", ctypes.c_double), ("tol_lnl", ctypes.c_double),
                 ("tol_t", ctypes.c_double), ("tol_newton", ctypes.c_double),
-                ("max_passes", ctypes.c_int32), ("max_newton", ctypes.c_int32)]
+                ("max_passes", ctypes.c_int32), ("max_newton", ctypes.c_int32),
+                ("prior_rate", ctypes.c_double)]
 
 
 _lib = None

@@ -132,6 +132,8 @@ pt_status check_opt(const pt_opt &o) {
     if (!(o.tol_lnl >= 0.0) || !(o.tol_t >= 0.0) || !(o.tol_newton >= 0.0))
         return fail(PT_EINVAL, "pt_opt: tolerances must be >= 0");
     if (o.max_passes < 1 || o.max_newton < 1) return fail(PT_EINVAL, "pt_opt: max_passes and max_newton must be >= 1");
+    if (!(o.prior_rate >= 0.0) || !std::isfinite(o.prior_rate))
+        return fail(PT_EINVAL, "pt_opt: prior_rate must be finite and >= 0");
     return PT_OK;
 }
 
@@ -144,6 +146,7 @@ pt::OptParams to_params(const pt_opt &o) {
     p.tol_newton = o.tol_newton;
     p.max_passes = o.max_passes;
     p.max_newton = o.max_newton;
+    p.prior_rate = o.prior_rate;
     return p;
 }
 
@@ -745,6 +748,7 @@ void pt_opt_default(int32_t precision, pt_opt *out) {
     out->t_max = 100.0;
     out->max_passes = 200;
     out->max_newton = 32;
+    out->prior_rate = 0.0;
     if (precision == PT_FP32) {
         out->tol_lnl = 1e-5;
         out->tol_t = 1e-3;

@@ -527,7 +527,8 @@ __device__ inline void newton_rows2(const T *tab, const double *wrow, size_t row
     }
 }
 
-// OP_NEWTON: safeguarded, projected Newton on the length of one edge.
+// OP_NEWTON: safeguarded, projected Newton on the length of one edge, for
+// lnL(t) - prior_rate * t (prior_rate 0: maximum likelihood).
 //  - the eigenbasis coefficients of this thread's patterns are computed once
 //    into `tab` (layout [k][row][4], rows = BS*ni pattern slots) and the
 //    pattern weights into `wrow` (in LDS, or in a per-block global buffer),
@@ -585,6 +586,7 @@ __device__ inline EdgeResult newton_edge(const TreeView<T> &v, int a, int b, dou
                                     d1, d2);
         }
         block_sum3<BS>(d0, d1, d2, red, parity);
+        d1 -= opt.prior_rate;  // MAP: the exponential prior's log density is linear in t
         if (iter >= opt.max_newton) break;
         if (d1 > 0.0) lo = t;
         else if (d1 < 0.0) hi = t;
@@ -768,6 +770,17 @@ __global__ void k_reduce(const BatchArgs a, bool grad, double *lnl, double *gout
     if (e == 0 && lnl) lnl[b] = s0;
 }
 
+// Log density of independent Exponential(rate) priors on the E lengths in
+// LDS, sum_e (log rate - rate t_e); 0 for rate 0.  Every thread reads all
+// lengths in the same order, so all hold the same value.
+__device__ inline double log_prior(const double *tl, int E, double rate) {
+    if (!(rate > 0.0)) return 0.0;
+    const double lr = log(rate);
+    double s = 0.0;
+    for (int e = 0; e < E; ++e) s += lr - rate * tl[e];
+    return s;
+}
+
 // Branch-length optimisation: one block owns one tree at a time, taken from
 // a work counter in the order given (largest trees first), and runs the
 // whole smoothing loop -- partial updates, per-edge Newton iterations with
@@ -872,6 +885,7 @@ __global__ void __launch_bounds__(BS) k_optimize(const BatchArgs a, double *brle
                 }
             }
             ++passes;
+            cur += log_prior(tl, E, opt.prior_rate);
             if (td.n_steady == 0 || (cur - prev < opt.tol_lnl && max_rel < opt.tol_t)) {
                 converged = true;
                 break;
@@ -899,7 +913,7 @@ __global__ void __launch_bounds__(BS) k_optimize(const BatchArgs a, double *brle
                 } else {
                     const Sums3 r = eval_edge<double, BS, KP>(vd, op.a, op.b, 0, ni, tl[op.dst], red, wx, parity);
                     parity = r.parity;
-                    cur = r.l0;
+                    cur = r.l0 + log_prior(tl, E, opt.prior_rate);
                 }
             }
         }

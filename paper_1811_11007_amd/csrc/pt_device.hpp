@@ -67,6 +67,7 @@ struct TreeDev {
 struct OptParams {
     double t_min, t_max, tol_lnl, tol_t, tol_newton;
     int32_t max_passes, max_newton;
+    double prior_rate;  // 0: maximum likelihood; > 0: exponential prior (MAP)
 };
 
 }  // namespace pt

@@ -170,6 +170,16 @@ def test_radius_masks_reject_bad_input():
     assert pt.pt_radius_masks(6, stack[:0], np.zeros(0, np.int32), 1).shape == (0, 9)
 
 
+def test_opt_defaults_and_layout():
+    """pt_opt as the binding lays it out matches the header (its size and the
+    prior_rate default of 0, maximum likelihood); no device is needed."""
+    import ctypes
+    assert ctypes.sizeof(pt._lib.pt_opt) == 56
+    for prec in (pt.PT_FP32, pt.PT_FP64):
+        o = pt.opt_default(prec)
+        assert o.prior_rate == 0.0 and o.max_passes == 200 and o.t_min == 1e-8
+
+
 def test_enumerated_topologies_have_distinct_keys():
     keys = {key_as_ints(pt.pt_topology_key(7, t), 7) for t in synth.all_topologies(7)}
     assert len(keys) == 945
