@@ -15,8 +15,14 @@
   of its endpoints (Methods, "Phylogenetic Topographer", the radius option;
   r = 0 is the new edge alone, r = 1 adds two neighbouring edges, r = -1 is
   every edge).
+* Split frequencies of a high-likelihood set: each topology weighted by its
+  maximised likelihood normalised over the set; a split's frequency is the
+  summed weight of the topologies holding it (Results, "Split Frequency
+  Comparison").  The majority-rule consensus keeps the splits above 1/2.
 """
 from __future__ import annotations
+
+import math
 
 import numpy as np
 
@@ -185,3 +191,21 @@ def double_factorial_count(n):
     for k in range(3, 2 * n - 4, 2):
         c *= k
     return c
+
+
+def split_frequencies(keys, lnl):
+    """{split: frequency} for topologies given by their keys (tuples of
+    splits) and maximised lnL values."""
+    lmax = max(lnl)
+    weights = [math.exp(l - lmax) for l in lnl]
+    total = sum(weights)
+    freq = {}
+    for k, w in zip(keys, weights):
+        for s in k:
+            freq[s] = freq.get(s, 0.0) + w / total
+    return freq
+
+
+def majority_splits(freq):
+    """The splits of frequency above 1/2."""
+    return {s for s, f in freq.items() if f > 0.5}

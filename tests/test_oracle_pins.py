@@ -559,3 +559,54 @@ def test_radius_edges_invariants(n, seed):
         v = edges[c][1] if u == edges[c][0] else edges[c][0]
         L = int(np.sum(dist[:n, u] < dist[:n, v]))
         assert len(sets[-1]) == 2 * L - 1
+
+
+# ------------------------------------------------------- split frequencies
+
+def _dfact(m):
+    return 1 if m <= 0 else m * _dfact(m - 2)
+
+
+@pytest.mark.parametrize("n", [5, 6, 7])
+def test_split_frequencies_uniform_closed_form(n):
+    """With equal likelihoods over all (2n-5)!! topologies, a split with sides
+    of a and n-a taxa lies in (2a-3)!! (2(n-a)-3)!! of them (a rooted tree
+    on each side)."""
+    tops = topo.all_topologies(n)
+    keys = [topo.key(t, n) for t in tops]
+    freq = topo.split_frequencies(keys, [0.0] * len(keys))
+    for s, f in freq.items():
+        a = bin(s).count("1")
+        assert f == pytest.approx(_dfact(2 * a - 3) * _dfact(2 * (n - a) - 3) / _dfact(2 * n - 5), rel=1e-12)
+    # every non-trivial split occurs
+    assert len(freq) == 2 ** (n - 1) - 1 - n
+
+
+def test_split_frequencies_by_hand():
+    # two 5-taxon topologies sharing the split {1,2} (bitmask 6), the first
+    # with {1,2,3} (14), the second with {1,2,4} (22); weights 3 : 1
+    keys = [(6, 14), (6, 22)]
+    freq = topo.split_frequencies(keys, [0.0, -math.log(3.0)])
+    assert freq == pytest.approx({6: 1.0, 14: 0.75, 22: 0.25}, rel=1e-15)
+    assert topo.majority_splits(freq) == {6, 14}
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_split_frequency_invariants(seed):
+    n = 7
+    rng = np.random.default_rng(seed)
+    tops = topo.all_topologies(n)
+    pick = rng.choice(len(tops), size=40, replace=False)
+    keys = [topo.key(tops[i], n) for i in pick]
+    lnl = rng.normal(-100.0, 3.0, size=len(keys))
+    freq = topo.split_frequencies(keys, lnl)
+    assert sum(freq.values()) == pytest.approx(n - 3, rel=1e-12)
+    assert all(0.0 < f <= 1.0 + 1e-12 for f in freq.values())
+    maj = sorted(topo.majority_splits(freq))
+    for x in maj:      # majority splits never conflict: as clades without
+        for y in maj:  # taxon 0 they are nested or disjoint
+            assert (x & y) == 0 or (x & y) == x or (x & y) == y
+    # one dominant topology: its splits, and only they, are in the majority
+    lnl2 = np.full(len(keys), -1000.0)
+    lnl2[5] = 0.0
+    assert topo.majority_splits(topo.split_frequencies(keys, lnl2)) == set(keys[5])
