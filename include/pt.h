@@ -262,6 +262,36 @@ pt_status pt_topology_keys(int32_t n, int32_t count, const int32_t *edges, uint6
 pt_status pt_radius_masks(int32_t n, int32_t count, const int32_t *edges, const int32_t *centres,
                           int32_t radius, uint8_t *out);
 
+/* ---------------------------------------------- high-likelihood set summary */
+
+/* Split frequencies of a high-likelihood set (Results, "Split Frequency
+ * Comparison": each topology is weighted by its maximised likelihood,
+ * normalised over the set, and a split's frequency is the summed weight of
+ * the topologies that contain it):
+ *   freq(s) = sum_{i : s in key_i} exp(lnl_i - lmax) / sum_i exp(lnl_i - lmax).
+ * keys uint64[count][n-3][W] as written by pt_topology_keys, lnl[count]
+ * finite.  Writes the *n_splits distinct splits, uint64[*n_splits][W], and
+ * their frequencies, by decreasing frequency (ties: the order of the splits
+ * as numbers).  cap is the capacity of splits / freq in splits; count *
+ * (n-3) always suffices.  EINVAL (with *n_splits set to the number needed)
+ * when cap is too small; EINVAL for count < 1, n < 4, a non-finite lnl or a
+ * key holding taxon 0 or a taxon >= n.  Host only. */
+pt_status pt_split_frequencies(int32_t n, int32_t count, const uint64_t *keys, const double *lnl, int32_t cap,
+                               int32_t *n_splits, uint64_t *splits, double *freq);
+
+/* Majority-rule consensus (Results, "Split Frequency Comparison"): the
+ * splits of frequency above 1/2, which are pairwise compatible, as a Newick
+ * string rooted at taxon 0.  Leaves are taxon indices; each clade carries its
+ * frequency as its label ("%.6f"); children appear in order of their
+ * smallest taxon, taxon 0 first at the root.  A star tree when no split
+ * passes.  splits / freq as pt_split_frequencies writes them (any order).
+ * out char[cap] receives the NUL-terminated string; *len_out is its size
+ * with the NUL.  EINVAL when cap is too small (len_out still set), or for a
+ * trivial split, one holding taxon 0, a frequency outside [0, 1], or
+ * incompatible or repeated splits above 1/2.  Host only. */
+pt_status pt_majority_consensus(int32_t n, int32_t n_splits, const uint64_t *splits, const double *freq, char *out,
+                                int32_t cap, int32_t *len_out);
+
 /* -------------------------------------------- warm-start network (learned) */
 
 /* Features of every NNI move of a tree whose lengths have been optimised,

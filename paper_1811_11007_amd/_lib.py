@@ -25,7 +25,7 @@ EXPORTS = [
     "pt_plan_create", "pt_plan_destroy", "pt_plan_set_graphs", "pt_plan_loglik",
     "pt_plan_optimize", "pt_plan_grad", "pt_plan_autotune", "pt_plan_traffic", "pt_plan_set_profile", "pt_plan_info",
     "pt_model_info", "pt_tree_check", "pt_nni_neighbors", "pt_topology_key", "pt_topology_keys",
-    "pt_nni_features", "pt_radius_masks",
+    "pt_nni_features", "pt_radius_masks", "pt_split_frequencies", "pt_majority_consensus",
     "pt_mlp_create", "pt_mlp_destroy", "pt_mlp_param_count", "pt_mlp_get_params", "pt_mlp_set_params",
     "pt_mlp_forward", "pt_mlp_warm_start", "pt_mlp_gradient", "pt_mlp_train_step",
 ]
@@ -113,6 +113,8 @@ def lib():
         L.pt_topology_keys.argtypes = [i32, i32, vp, vp]
         L.pt_nni_features.argtypes = [i32, vp, vp, vp]
         L.pt_radius_masks.argtypes = [i32, i32, vp, vp, i32, vp]
+        L.pt_split_frequencies.argtypes = [i32, i32, vp, vp, i32, vp, vp, vp]
+        L.pt_majority_consensus.argtypes = [i32, i32, vp, vp, vp, i32, vp]
         L.pt_mlp_create.argtypes = [vp, i32, i32, i32, vp, P(vp)]
         L.pt_mlp_destroy.argtypes = [vp]
         L.pt_mlp_destroy.restype = None
@@ -332,6 +334,36 @@ def pt_radius_masks(n, edges, centres, radius):
     out = np.zeros((e.shape[0], e.shape[1]), np.uint8)
     check(lib().pt_radius_masks(int(n), int(e.shape[0]), _ptr(e), _ptr(c), int(radius), _ptr(out)))
     return out
+
+
+def pt_split_frequencies(n, keys, lnl):
+    """Split frequencies of a set of topologies (keys uint64[count][n-3][W]
+    from pt_topology_keys, lnl[count]): returns (splits uint64[m][W],
+    freq[m]) by decreasing frequency."""
+    k = np.ascontiguousarray(keys, dtype=np.uint64)
+    lv = np.ascontiguousarray(lnl, dtype=np.float64)
+    W = (n + 63) // 64
+    if k.ndim != 3 or k.shape[1:] != (max(n - 3, 0), W) or lv.shape != (k.shape[0],):
+        raise ValueError("keys must be [count][n-3][W] and lnl [count]")
+    cap = max(1, k.shape[0] * max(n - 3, 0))
+    splits = np.zeros((cap, W), np.uint64)
+    freq = np.zeros(cap)
+    m = ctypes.c_int32(0)
+    check(lib().pt_split_frequencies(int(n), int(k.shape[0]), _ptr(k), _ptr(lv), int(cap), ctypes.byref(m),
+                                     _ptr(splits), _ptr(freq)))
+    return splits[:m.value].copy(), freq[:m.value].copy()
+
+
+def pt_majority_consensus(n, splits, freq):
+    """Majority-rule consensus tree (Newick, rooted at taxon 0, clade labels
+    = split frequencies)."""
+    s = np.ascontiguousarray(splits, dtype=np.uint64)
+    f = np.ascontiguousarray(freq, dtype=np.float64)
+    cap = 64 + 24 * int(n)
+    buf = ctypes.create_string_buffer(cap)
+    ln = ctypes.c_int32(0)
+    check(lib().pt_majority_consensus(int(n), int(len(f)), _ptr(s), _ptr(f), buf, cap, ctypes.byref(ln)))
+    return buf.value.decode()
 
 
 def _dptr(t):

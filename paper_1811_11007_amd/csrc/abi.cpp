@@ -979,6 +979,24 @@ pt_status pt_radius_masks(int32_t n, int32_t count, const int32_t *edges, const 
     return PT_OK;
 }
 
+pt_status pt_split_frequencies(int32_t n, int32_t count, const uint64_t *keys, const double *lnl, int32_t cap,
+                               int32_t *n_splits, uint64_t *splits, double *freq) {
+    if (!keys || !lnl || !n_splits || (cap > 0 && (!splits || !freq)) || cap < 0)
+        return fail(PT_EINVAL, "bad arguments");
+    std::string err;
+    pt_status st = pt::split_frequencies(n, count, keys, lnl, cap, n_splits, splits, freq, err);
+    return st ? fail(st, err) : PT_OK;
+}
+
+pt_status pt_majority_consensus(int32_t n, int32_t n_splits, const uint64_t *splits, const double *freq, char *out,
+                                int32_t cap, int32_t *len_out) {
+    if (n_splits < 0 || (n_splits > 0 && (!splits || !freq)) || !out || !len_out || cap < 1)
+        return fail(PT_EINVAL, "bad arguments");
+    std::string err;
+    pt_status st = pt::majority_consensus(n, n_splits, splits, freq, out, cap, len_out, err);
+    return st ? fail(st, err) : PT_OK;
+}
+
 pt_status pt_nni_features(int32_t n, const int32_t *edges, const double *brlen, float *out) {
     if (!edges || !brlen || !out) return fail(PT_EINVAL, "NULL argument");
     std::string err;

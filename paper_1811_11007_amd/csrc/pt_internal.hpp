@@ -49,4 +49,10 @@ pt_status topology_key(int n, const int32_t *edges, uint64_t *out, std::string &
 pt_status nni_features(int n, const int32_t *edges, const double *brlen, float *out, std::string &err);
 pt_status radius_mask(int n, const int32_t *edges, int centre, int r, uint8_t *out, std::string &err);
 
+// ------------------------------------------------------------ HLS summaries
+pt_status split_frequencies(int n, int count, const uint64_t *keys, const double *lnl, int cap, int32_t *n_out,
+                            uint64_t *splits, double *freq, std::string &err);
+pt_status majority_consensus(int n, int count, const uint64_t *splits, const double *freq, char *out, int cap,
+                             int32_t *len_out, std::string &err);
+
 }  // namespace pt

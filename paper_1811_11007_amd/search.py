@@ -222,6 +222,17 @@ class ThresholdSearch:
                             batches=stats["batches"], warm_better=stats["warm_better"], samples=samples)
 
 
+def hls_summary(n, result):
+    """Split frequencies and majority-rule consensus of a search's good set
+    (Results, "Split Frequency Comparison": topologies weighted by their
+    normalised maximised likelihoods).  Returns (splits uint64[m][W],
+    frequencies, consensus Newick)."""
+    good = list(result.good.values())
+    keys = L.pt_topology_keys(n, np.stack([g[1] for g in good]))
+    splits, freq = L.pt_split_frequencies(n, keys, np.array([g[0] for g in good]))
+    return splits, freq, L.pt_majority_consensus(n, splits, freq)
+
+
 def main():
     """Threshold searches at several proposal radii on one synthetic workload,
     one JSON line per radius: good, visited and proposed counts, time, and
@@ -266,7 +277,8 @@ def main():
             "good": len(good), "visited": res.visited, "proposed": res.proposed, "lmax": round(res.lmax, 4),
             "seconds": round(secs, 2), "proposal_seconds": round(res.proposal_time_s, 2),
             "missed": None if full is None else len(full - good),
-            "extra": None if full is None else len(good - full)}), flush=True)
+            "extra": None if full is None else len(good - full),
+            "consensus": hls_summary(aln.n_taxa, res)[2]}), flush=True)
     ctx.close()
 
 

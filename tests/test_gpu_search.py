@@ -15,6 +15,8 @@ optimises every topology from six starts; a threshold is used only if no
 topology's optima straddle it (or lie within 1e-3 of it), so that the
 superlevel set does not depend on the starts.
 """
+import math
+
 import numpy as np
 import pytest
 
@@ -22,7 +24,7 @@ import paper_1811_11007_amd as pt
 import synth
 from oracle import core as oc
 from oracle import topo
-from paper_1811_11007_amd.search import ThresholdSearch
+from paper_1811_11007_amd.search import ThresholdSearch, hls_summary
 
 pytestmark = pytest.mark.gpu
 
@@ -93,10 +95,22 @@ def test_search_equals_superlevel_component(ctx, seed):
     got = {topo.key(v[1], n): v[0] for v in res.good.values()}
     assert set(got) == comp
     assert abs(res.lmax - lmax) <= 1e-6 * abs(lmax)
+    delta = 0.0
     for k, l in got.items():
         i = keys.index(k)
         # one of the topology's optima (the search starts from inherited lengths)
         assert low[i] - 1e-6 * abs(l) <= l <= lnl[i] + 1e-6 * abs(l)
+        delta = max(delta, abs(l - lnl[i]))
+    # HLS summary: split frequencies of the good set against the oracle's
+    # from its own optima over the component.  Each weight ratio moves by at
+    # most exp(2 delta), which bounds every frequency's error.
+    splits, freq, newick = hls_summary(n, res)
+    want = topo.split_frequencies(sorted(comp), [lnl[keys.index(k)] for k in sorted(comp)])
+    assert {int(s[0]) for s in splits} == set(want)
+    bound = math.expm1(2 * delta) + 1e-12
+    for s, f in zip(splits, freq):
+        assert abs(f - want[int(s[0])]) <= bound
+    say("HLS consensus", newick, "max |dlnL|", delta)
     for radius in (0, 1, 2):
         res_r = ThresholdSearch(ctx, A, threshold=T, radius=radius, precision=pt.PT_FP64, batch=64).run(start)
         got_r = {topo.key(v[1], n) for v in res_r.good.values()}

@@ -180,6 +180,108 @@ def test_opt_defaults_and_layout():
         assert o.prior_rate == 0.0 and o.max_passes == 200 and o.t_min == 1e-8
 
 
+def parse_consensus(newick, n):
+    """{clade bitmask without taxon 0: label} of a Newick string rooted at
+    taxon 0 with numeric leaves and clade labels, and the leaf set."""
+    pos = 0
+    clades = {}
+    leaves = set()
+
+    def node():
+        nonlocal pos
+        if newick[pos] == "(":
+            pos += 1
+            mask = 0
+            while True:
+                mask |= node()
+                if newick[pos] == ",":
+                    pos += 1
+                    continue
+                assert newick[pos] == ")"
+                pos += 1
+                break
+            j = pos
+            while pos < len(newick) and newick[pos] not in ",);":
+                pos += 1
+            if newick[j:pos]:
+                clades[mask] = float(newick[j:pos])
+            return mask
+        j = pos
+        while newick[pos] not in ",);":
+            pos += 1
+        leaf = int(newick[j:pos])
+        leaves.add(leaf)
+        return 0 if leaf == 0 else 1 << leaf
+
+    node()
+    assert newick[pos:] == ";"
+    return clades, leaves
+
+
+@pytest.mark.parametrize("n,seed,count", [(6, 31, 30), (9, 32, 200), (70, 33, 40)])
+def test_split_frequencies_and_consensus_match_oracle(n, seed, count):
+    rng = np.random.default_rng(seed)
+    trees = []
+    e, _ = synth.yule_tree(n, rng)
+    for _ in range(count):  # a random NNI walk: sets with shared splits
+        ne, _, _ = pt.pt_nni_neighbors(n, e)
+        e = ne[rng.integers(len(ne))]
+        trees.append(e)
+    keys = pt.pt_topology_keys(n, np.stack(trees))
+    lnl = rng.normal(-5000.0, 2.0, size=count)
+    splits, freq = pt.pt_split_frequencies(n, keys, lnl)
+    W = (n + 63) // 64
+    as_int = [sum(int(r[w]) << (64 * w) for w in range(W)) for r in splits]
+    want = topo.split_frequencies([key_as_ints(k, n) for k in keys], lnl)
+    assert set(as_int) == set(want)
+    for s, f in zip(as_int, freq):
+        assert f == pytest.approx(want[s], rel=1e-12, abs=1e-300)
+    assert np.all(np.diff(freq) <= 0)
+    newick = pt.pt_majority_consensus(n, splits, freq)
+    clades, leaves = parse_consensus(newick, n)
+    assert leaves == set(range(n))
+    assert set(clades) == topo.majority_splits(want)
+    for c, lab in clades.items():
+        assert abs(lab - want[c]) <= 5e-7
+
+
+def test_consensus_of_one_topology_and_star():
+    n = 8
+    e, _ = synth.yule_tree(n, np.random.default_rng(34))
+    k = pt.pt_topology_keys(n, np.asarray(e, np.int32)[None])
+    splits, freq = pt.pt_split_frequencies(n, k, [-10.0])
+    assert np.all(freq == 1.0)
+    clades, _ = parse_consensus(pt.pt_majority_consensus(n, splits, freq), n)
+    assert set(clades) == set(key_as_ints(k[0], n))
+    assert pt.pt_majority_consensus(n, splits, freq * 0.5) == "(0,1,2,3,4,5,6,7);"
+
+
+def test_hls_summary_rejects_bad_input():
+    import ctypes
+    n = 6
+    tops = synth.all_topologies(n)[:4]
+    keys = pt.pt_topology_keys(n, np.stack(tops))
+    for bad_lnl in ([0.0, np.nan, 0.0, 0.0], [0.0, np.inf, 0.0, 0.0]):
+        with pytest.raises(pt.PTError):
+            pt.pt_split_frequencies(n, keys, bad_lnl)
+    k0 = keys.copy()
+    k0[1, 0, 0] |= 1  # taxon 0 in a split
+    with pytest.raises(pt.PTError):
+        pt.pt_split_frequencies(n, k0, np.zeros(4))
+    # a capacity below the number of distinct splits reports the number needed
+    out = np.zeros((2, 1), np.uint64)
+    fr = np.zeros(2)
+    m = ctypes.c_int32(0)
+    rc = pt.lib().pt_split_frequencies(n, 4, keys.ctypes.data_as(ctypes.c_void_p),
+                                       np.zeros(4).ctypes.data_as(ctypes.c_void_p), 2, ctypes.byref(m),
+                                       out.ctypes.data_as(ctypes.c_void_p), fr.ctypes.data_as(ctypes.c_void_p))
+    assert rc == -1 and m.value == len(pt.pt_split_frequencies(n, keys, np.zeros(4))[0])
+    # consensus: incompatible splits above 1/2, a trivial split, frequency > 1
+    for s, f in (([[6], [10]], [0.6, 0.6]), ([[2]], [0.9]), ([[6]], [1.5])):
+        with pytest.raises(pt.PTError):
+            pt.pt_majority_consensus(n, np.array(s, np.uint64), f)
+
+
 def test_enumerated_topologies_have_distinct_keys():
     keys = {key_as_ints(pt.pt_topology_key(7, t), 7) for t in synth.all_topologies(7)}
     assert len(keys) == 945

@@ -81,6 +81,12 @@ def test_search_logic_against_brute_force(seed):
     got = {topo.key(v[1], n) for v in res.good.values()}
     assert got == comp
     assert abs(res.lmax - lmax) < 1e-9 * abs(lmax)
+    # the good set's split frequencies and consensus (host library calls)
+    splits, freq, newick = S.hls_summary(n, res)
+    want = topo.split_frequencies([topo.key(v[1], n) for v in res.good.values()],
+                                  [v[0] for v in res.good.values()])
+    assert {int(x[0]): f for x, f in zip(splits, freq)} == pytest.approx(want, rel=1e-12)
+    assert newick.startswith("(0,") and newick.endswith(");")
     # batches of at most 16 trees; every good topology was visited
     assert max(s.batches_seen) <= 16
     assert res.visited >= len(res.good)
