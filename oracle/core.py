@@ -10,6 +10,7 @@ the likelihood).
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import subprocess
 
@@ -195,3 +196,44 @@ def optimize(data: Data, edges, brlen, mask=None, t_min=T_MIN, t_max=T_MAX,
                              float(tol_t), float(tol_newton), int(max_passes), int(max_newton),
                              float(prior_rate), _d(l), _i(ps), _i(cv)))
     return float(l[0]), b, int(ps[0]), bool(cv[0])
+
+
+# Bounds of the Gamma shape in per-topology model optimisation (the paper
+# leaves them to its likelihood library; a reading).
+ALPHA_MIN, ALPHA_MAX = 0.02, 100.0
+
+
+def with_alpha(data: Data, alpha):
+    """The same patterns and model with another Gamma shape."""
+    return Data(data.tips, data.w, data.rates, data.freqs, alpha, data.K)
+
+
+def optimize_alpha(data: Data, edges, brlen, alpha0, alpha_min=ALPHA_MIN, alpha_max=ALPHA_MAX,
+                   tol_lnl=1e-11, max_rounds=500):
+    """Joint maximum of lnL over the branch lengths and the Gamma shape alpha
+    (the paper's optional per-topology model optimisation, Methods,
+    "Phylogenetic Topographer"): rounds of a full branch-length optimisation
+    at fixed alpha, then a bounded one-dimensional maximisation over log alpha
+    at fixed lengths (scipy's bounded Brent minimiser as the primitive),
+    until a round gains less than tol_lnl; then the lengths once more at the
+    final alpha.  Returns (lnL, lengths, alpha, rounds)."""
+    from scipy.optimize import minimize_scalar
+
+    alpha = min(max(float(alpha0), alpha_min), alpha_max)
+    b = np.asarray(brlen, dtype=np.float64).copy()
+    prev = -np.inf
+    cur = -np.inf
+    rounds = 0
+    for rounds in range(1, max_rounds + 1):
+        cur, b, _, _ = optimize(with_alpha(data, alpha), edges, b)
+        if data.K > 1:
+            res = minimize_scalar(lambda x: -loglik(with_alpha(data, math.exp(x)), edges, b),
+                                  bounds=(math.log(alpha_min), math.log(alpha_max)), method="bounded",
+                                  options={"xatol": 1e-10})
+            if -res.fun > cur:
+                alpha, cur = math.exp(res.x), -res.fun
+        if cur - prev < tol_lnl:
+            break
+        prev = cur
+    cur, b, _, _ = optimize(with_alpha(data, alpha), edges, b)
+    return cur, b, alpha, rounds

@@ -610,3 +610,37 @@ def test_split_frequency_invariants(seed):
     lnl2 = np.full(len(keys), -1000.0)
     lnl2[5] = 0.0
     assert topo.majority_splits(topo.split_frequencies(keys, lnl2)) == set(keys[5])
+
+
+# ------------------------------------------- per-topology Gamma-shape optimum
+
+@pytest.mark.parametrize("seed", [5, 6])
+def test_alpha_optimum_against_profile_grid(seed):
+    """The joint optimum over lengths and alpha must beat every point of a
+    profile-likelihood grid (lengths fully optimised at each fixed alpha,
+    with the pinned length optimiser), sit between the grid neighbours of
+    the best grid point, and be stationary in alpha and in every length."""
+    rng = np.random.default_rng(seed)
+    edges, brlen = synth.yule_tree(6, rng, mean=0.1)
+    aln = synth.make_alignment(edges, brlen, 6, 400, rng, alpha=0.5, n_cats=4)
+    D = oc.Data.from_alignment(aln)
+    l, b, a, _ = oc.optimize_alpha(D, edges, brlen, 1.0)
+    grid = np.geomspace(0.05, 20.0, 31)
+    prof = np.array([oc.optimize(oc.with_alpha(D, g), edges, brlen)[0] for g in grid])
+    i = int(np.argmax(prof))
+    assert l >= prof[i] - 1e-9
+    assert grid[max(i - 1, 0)] <= a <= grid[min(i + 1, len(grid) - 1)]
+    h = 1e-4
+    dl = (oc.loglik(oc.with_alpha(D, a * math.exp(h)), edges, b) -
+          oc.loglik(oc.with_alpha(D, a * math.exp(-h)), edges, b)) / (2 * h)
+    assert abs(dl) < 1e-4
+    _kkt(oc.with_alpha(D, a), edges, b)
+    assert l == pytest.approx(oc.loglik(oc.with_alpha(D, a), edges, b), abs=1e-9)
+
+
+def test_alpha_irrelevant_without_categories():
+    edges, brlen, aln = small_case(5, 27, sites=200, mean=0.1)
+    D = oc.Data(aln.tips, aln.weights, aln.rates, aln.freqs, 0.7, 1)
+    l, _, a, rounds = oc.optimize_alpha(D, edges, brlen, 0.7)
+    assert a == 0.7 and rounds <= 2
+    assert l == pytest.approx(oc.optimize(D, edges, brlen)[0], abs=1e-12)
