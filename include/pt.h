@@ -192,6 +192,39 @@ pt_status pt_plan_grad(pt_plan *plan, const double *d_brlen, double *d_lnl,
 pt_status pt_plan_autotune(pt_plan *plan, const double *d_brlen, const pt_opt *opt,
                            int32_t *block, int32_t *items);
 
+/* Per-tree Gamma shapes (the paper's optional model optimisation, Methods,
+ * "Phylogenetic Topographer": in its simplified case, the shape of the
+ * Gamma rate distribution is optimised for each visited topology).
+ * alpha: host double[n_trees], each finite and > 0, or NULL to return every
+ * tree to its alignment's own shape.  Every later call on this plan uses
+ * tree b's K discrete-Gamma category means at alpha[b] (Yang 1994, the same
+ * discretisation as pt_aln_create); trees with one category are unchanged.
+ * The per-tree model descriptors are copied on `stream`, and the call
+ * returns after the copy (not to be captured into a graph). */
+pt_status pt_plan_set_alpha(pt_plan *plan, const double *alpha, void *stream);
+
+/* Joint optimisation of every tree's branch lengths and Gamma shape: the
+ * lengths are optimised at fixed shapes (pt_plan_optimize with opt), then,
+ * in each round, the shape of every active tree at fixed lengths by Brent's
+ * one-dimensional minimiser on log alpha over [alpha_min, alpha_max] (Brent
+ * 1973; the trees in lockstep, one batched pt_plan_loglik per step, each
+ * minimisation ending when its bracket is below tol_alpha in log alpha)
+ * followed by all lengths again.  A tree whose lnL, after a round's length
+ * optimisation, rose by less than opt->tol_lnl keeps its shape from then
+ * on; the call ends when no tree is active or after max_rounds rounds,
+ * always on a length optimisation.  The plan needs
+ * PT_PLAN_OPTIMIZE | PT_PLAN_LOGLIK.  d_brlen_inout: device double[total
+ * edges]; alpha_inout: host double[n_trees], starting shapes inside the
+ * bounds, overwritten with the optimised ones (the plan keeps them, see
+ * pt_plan_set_alpha); lnl_out: host double[n_trees], lnL at the returned
+ * shapes and lengths (the optimiser's objective); rounds_out: host, NULL
+ * ok, the number of shape updates.
+ * Synchronises `stream` after every step.  EINVAL for bad bounds, a start
+ * outside them, tol_alpha <= 0 or max_rounds < 1. */
+pt_status pt_plan_optimize_alpha(pt_plan *plan, double *d_brlen_inout, const pt_opt *opt, double *alpha_inout,
+                                 double alpha_min, double alpha_max, double tol_alpha, int32_t max_rounds,
+                                 double *lnl_out, int32_t *rounds_out, void *stream);
+
 /* Algorithmic device-memory bytes one run of `kind` moves: every partial,
  * scaler, tip code and weight its programs read or write once per use
  * (Newton iterations and transition matrices add none).  For

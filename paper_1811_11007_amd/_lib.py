@@ -23,7 +23,8 @@ EXPORTS = [
     "pt_last_error", "pt_ctx_create", "pt_ctx_destroy", "pt_aln_create", "pt_aln_destroy",
     "pt_opt_default", "pt_batch_loglik", "pt_batch_optimize_branches", "pt_batch_branch_grad",
     "pt_plan_create", "pt_plan_destroy", "pt_plan_set_graphs", "pt_plan_loglik",
-    "pt_plan_optimize", "pt_plan_grad", "pt_plan_autotune", "pt_plan_traffic", "pt_plan_set_profile", "pt_plan_info",
+    "pt_plan_optimize", "pt_plan_set_alpha", "pt_plan_optimize_alpha", "pt_plan_grad", "pt_plan_autotune",
+    "pt_plan_traffic", "pt_plan_set_profile", "pt_plan_info",
     "pt_model_info", "pt_tree_check", "pt_nni_neighbors", "pt_topology_key", "pt_topology_keys",
     "pt_nni_features", "pt_radius_masks", "pt_split_frequencies", "pt_majority_consensus",
     "pt_mlp_create", "pt_mlp_destroy", "pt_mlp_param_count", "pt_mlp_get_params", "pt_mlp_set_params",
@@ -101,6 +102,9 @@ def lib():
         L.pt_plan_set_graphs.argtypes = [vp, i32]
         L.pt_plan_loglik.argtypes = [vp, vp, vp, vp]
         L.pt_plan_optimize.argtypes = [vp, vp, P(pt_opt), vp, vp, vp, vp]
+        L.pt_plan_set_alpha.argtypes = [vp, vp, vp]
+        L.pt_plan_optimize_alpha.argtypes = [vp, vp, P(pt_opt), vp, ctypes.c_double, ctypes.c_double,
+                                             ctypes.c_double, i32, vp, P(i32), vp]
         L.pt_plan_grad.argtypes = [vp, vp, vp, vp, vp, vp]
         L.pt_plan_autotune.argtypes = [vp, vp, P(pt_opt), P(i32), P(i32)]
         L.pt_plan_info.argtypes = [vp, P(i32), P(i64), P(i64)]
@@ -455,6 +459,25 @@ class Plan:
             ctypes.c_void_p(d_passes.data_ptr()) if d_passes is not None else None,
             ctypes.c_void_p(d_status.data_ptr()) if d_status is not None else None,
             self._stream(stream)))
+
+    def set_alpha(self, alpha, stream=None):
+        """Per-tree Gamma shapes (host array [n_trees]), or None for each
+        alignment's own."""
+        a = None if alpha is None else np.ascontiguousarray(alpha, dtype=np.float64)
+        check(lib().pt_plan_set_alpha(self.h, _ptr(a), self._stream(stream)))
+
+    def optimize_alpha(self, d_brlen, alpha, alpha_min=0.02, alpha_max=100.0, tol_alpha=1e-4, max_rounds=50,
+                       opt=None, stream=None):
+        """Joint lengths + Gamma-shape optimisation; returns (lnL, alpha,
+        rounds) as numpy arrays / int; d_brlen is updated in place."""
+        a = np.array(alpha, dtype=np.float64, copy=True)
+        lnl = np.zeros(len(a))
+        r = ctypes.c_int32(0)
+        check(lib().pt_plan_optimize_alpha(self.h, ctypes.c_void_p(d_brlen.data_ptr()),
+                                           ctypes.byref(opt) if opt else None, _ptr(a), float(alpha_min),
+                                           float(alpha_max), float(tol_alpha), int(max_rounds), _ptr(lnl),
+                                           ctypes.byref(r), self._stream(stream)))
+        return lnl, a, r.value
 
     def grad(self, d_brlen, d_lnl, d_grad, d_hess=None, stream=None):
         check(lib().pt_plan_grad(self.h, ctypes.c_void_p(d_brlen.data_ptr()),

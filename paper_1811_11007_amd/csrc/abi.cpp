@@ -102,7 +102,9 @@ struct pt_plan {
     // host copies for traffic accounting
     std::vector<Op> ops_h;
     std::vector<TreeDev> tll_h, tgr_h, top_h;
-    std::vector<AlnDev> alns_h;
+    std::vector<AlnDev> alns_h;       // per tree, as on the device
+    std::vector<AlnDev> alns_base_h;  // per tree, the alignment's own model
+    double *d_alpha_lnl = nullptr;    // per tree, for the Gamma-shape search
 };
 
 namespace {
@@ -297,7 +299,7 @@ pt_status plan_build(pt_ctx *ctx, pt_aln *const *alns, int32_t n_alns, const pt_
         pl->max_E = std::max(pl->max_E, E);
         pl->tree_E.push_back(E);
         TreeDev base{};
-        base.aln = trees->aln_index[b];
+        base.aln = b;  // every tree has a descriptor of its own (per-tree Gamma shape)
         base.n_edges = E;
         base.n_slots = t.n_slots();
         base.clv_off = clv_off;
@@ -366,7 +368,8 @@ pt_status plan_build(pt_ctx *ctx, pt_aln *const *alns, int32_t n_alns, const pt_
     pl->tll_h = tll;
     pl->tgr_h = tgr;
     pl->top_h = top;
-    for (int i = 0; i < n_alns; ++i) pl->alns_h.push_back(alns[i]->desc);
+    for (int b = 0; b < B; ++b) pl->alns_h.push_back(alns[trees->aln_index[b]]->desc);
+    pl->alns_base_h = pl->alns_h;
 
     // arena cap
     int64_t need = clv_off * (int64_t)store_bytes(precision) + cnt_off * 2 + pm_off * 8 +
@@ -379,11 +382,9 @@ pt_status plan_build(pt_ctx *ctx, pt_aln *const *alns, int32_t n_alns, const pt_
     int dev_prev = 0;
     PT_HIP(hipGetDevice(&dev_prev));
     PT_HIP(hipSetDevice(ctx->device));
-    // descriptors
-    std::vector<AlnDev> ad(n_alns);
-    for (int i = 0; i < n_alns; ++i) ad[i] = alns[i]->desc;
-    if ((st = dev_alloc(pl.get(), &pl->d_alns, sizeof(AlnDev) * n_alns))) return st;
-    PT_HIP(hipMemcpy(pl->d_alns, ad.data(), sizeof(AlnDev) * n_alns, hipMemcpyHostToDevice));
+    // descriptors, one per tree
+    if ((st = dev_alloc(pl.get(), &pl->d_alns, sizeof(AlnDev) * std::max(1, B)))) return st;
+    if (B) PT_HIP(hipMemcpy(pl->d_alns, pl->alns_h.data(), sizeof(AlnDev) * B, hipMemcpyHostToDevice));
     if ((st = dev_alloc(pl.get(), &pl->d_ops, sizeof(Op) * ops.size()))) return st;
     if (!ops.empty()) PT_HIP(hipMemcpy(pl->d_ops, ops.data(), sizeof(Op) * ops.size(), hipMemcpyHostToDevice));
     auto up_trees = [&](std::vector<TreeDev> &v, TreeDev **d) -> pt_status {
@@ -870,6 +871,187 @@ pt_status pt_plan_autotune(pt_plan *plan, const double *d_brlen, const pt_opt *o
     plan->ctx->tuned[std::make_tuple(plan->precision, plan->kp, plan->max_P)] = best_b;
     if (block) *block = plan->opt_block;
     if (items) *items = plan->opt_items;
+    return PT_OK;
+}
+
+namespace {
+
+// Brent's minimiser of a function of one variable on [a, b] (R. P. Brent,
+// "Algorithms for Minimization without Derivatives", 1973, chapter 5):
+// golden-section steps, replaced by a parabola through the three best points
+// when its minimum lies well inside the bracket and the step is shrinking.
+// Reverse communication -- point() is the abscissa to evaluate next and
+// tell() takes its value -- so that the minimisations of many trees advance
+// in lockstep, one batched likelihood launch per step.
+struct BrentMin {
+    double a = 0, b = 0, x = 0, w = 0, v = 0, fx = 0, fw = 0, fv = 0, d = 0, e = 0, u = 0, tol = 0;
+    bool started = false, done = false;
+
+    void init(double lo, double hi, double x0, double tol_) {
+        a = lo;
+        b = hi;
+        x = w = v = u = std::min(std::max(x0, lo), hi);
+        d = e = 0.0;
+        tol = tol_;
+        started = done = false;
+    }
+    double point() const { return u; }
+    void tell(double fu) {
+        if (!started) {
+            fx = fw = fv = fu;
+            started = true;
+        } else if (fu <= fx) {
+            if (u >= x) a = x; else b = x;
+            v = w; fv = fw;
+            w = x; fw = fx;
+            x = u; fx = fu;
+        } else {
+            if (u < x) a = u; else b = u;
+            if (fu <= fw || w == x) {
+                v = w; fv = fw;
+                w = u; fw = fu;
+            } else if (fu <= fv || v == x || v == w) {
+                v = u; fv = fu;
+            }
+        }
+        step();
+    }
+
+  private:
+    void step() {
+        const double golden = 0.5 * (3.0 - std::sqrt(5.0));
+        const double xm = 0.5 * (a + b);
+        const double tol1 = 1.5e-8 * std::fabs(x) + tol / 3.0, tol2 = 2.0 * tol1;
+        if (std::fabs(x - xm) <= tol2 - 0.5 * (b - a)) {
+            done = true;
+            u = x;
+            return;
+        }
+        bool parabola = false;
+        if (std::fabs(e) > tol1) {
+            double r = (x - w) * (fx - fv), q = (x - v) * (fx - fw), p = (x - v) * q - (x - w) * r;
+            q = 2.0 * (q - r);
+            if (q > 0.0) p = -p;
+            q = std::fabs(q);
+            const double e_prev = e;
+            e = d;
+            if (std::fabs(p) < std::fabs(0.5 * q * e_prev) && p > q * (a - x) && p < q * (b - x)) {
+                d = p / q;
+                parabola = true;
+                const double t = x + d;
+                if (t - a < tol2 || b - t < tol2) d = std::copysign(tol1, xm - x);
+            }
+        }
+        if (!parabola) {
+            e = x >= xm ? a - x : b - x;
+            d = golden * e;
+        }
+        u = x + (std::fabs(d) >= tol1 ? d : std::copysign(tol1, d));
+    }
+};
+
+pt_status set_alpha(pt_plan *pl, const double *alpha, hipStream_t s) {
+    std::string err;
+    for (int b = 0; b < pl->n_trees; ++b) {
+        AlnDev d = pl->alns_base_h[b];
+        if (alpha && d.K > 1) {
+            pt_status st = pt::gamma_category_rates(alpha[b], d.K, d.rate, err);
+            if (st) return fail(st, "tree " + std::to_string(b) + ": " + err);
+            for (int k = d.K; k < pt::kMaxCats; ++k) d.rate[k] = 0.0;
+        }
+        pl->alns_h[b] = d;
+    }
+    if (pl->n_trees == 0) return PT_OK;
+    PT_HIP(hipSetDevice(pl->ctx->device));
+    PT_HIP(hipMemcpyAsync(pl->d_alns, pl->alns_h.data(), sizeof(AlnDev) * pl->n_trees, hipMemcpyHostToDevice, s));
+    PT_HIP(hipStreamSynchronize(s));
+    return PT_OK;
+}
+
+}  // namespace
+
+pt_status pt_plan_set_alpha(pt_plan *plan, const double *alpha, void *stream) {
+    if (!plan) return fail(PT_EINVAL, "plan is NULL");
+    if (alpha)
+        for (int b = 0; b < plan->n_trees; ++b)
+            if (!(alpha[b] > 0.0) || !std::isfinite(alpha[b]))
+                return fail(PT_EINVAL, "alpha[" + std::to_string(b) + "] must be finite and > 0");
+    return set_alpha(plan, alpha, (hipStream_t)stream);
+}
+
+pt_status pt_plan_optimize_alpha(pt_plan *plan, double *d_brlen_inout, const pt_opt *opt, double *alpha_inout,
+                                 double alpha_min, double alpha_max, double tol_alpha, int32_t max_rounds,
+                                 double *lnl_out, int32_t *rounds_out, void *stream) {
+    if (!plan || (plan->kinds & (PT_PLAN_OPTIMIZE | PT_PLAN_LOGLIK)) != (PT_PLAN_OPTIMIZE | PT_PLAN_LOGLIK))
+        return fail(PT_EINVAL, "plan was not created with PT_PLAN_OPTIMIZE | PT_PLAN_LOGLIK");
+    const int B = plan->n_trees;
+    if (B && (!d_brlen_inout || !alpha_inout || !lnl_out)) return fail(PT_EINVAL, "NULL argument");
+    if (!(alpha_min > 0.0) || !(alpha_max > alpha_min) || !std::isfinite(alpha_max))
+        return fail(PT_EINVAL, "need 0 < alpha_min < alpha_max < inf");
+    if (!(tol_alpha > 0.0) || max_rounds < 1) return fail(PT_EINVAL, "need tol_alpha > 0 and max_rounds >= 1");
+    for (int b = 0; b < B; ++b)
+        if (!(alpha_inout[b] >= alpha_min && alpha_inout[b] <= alpha_max))
+            return fail(PT_EINVAL, "alpha[" + std::to_string(b) + "] outside [alpha_min, alpha_max]");
+    pt_opt o;
+    if (opt) o = *opt; else pt_opt_default(plan->precision, &o);
+    pt_status st = check_opt(o);
+    if (st) return st;
+    if (B == 0) {
+        if (rounds_out) *rounds_out = 0;
+        return PT_OK;
+    }
+    const pt::OptParams p = to_params(o);
+    hipStream_t s = (hipStream_t)stream;
+    if (!plan->d_alpha_lnl && (st = dev_alloc(plan, &plan->d_alpha_lnl, sizeof(double) * B))) return st;
+    std::vector<double> alpha(alpha_inout, alpha_inout + B), trial(B), f(B), best(B, -INFINITY), cur(B);
+    std::vector<char> active(B, 1);  // trees whose shape still moves
+    std::vector<BrentMin> br(B);
+    const double lo = std::log(alpha_min), hi = std::log(alpha_max);
+    int rounds = 0;
+    for (;;) {
+        // lengths at the current shapes; their lnL (the optimiser's, from
+        // FP64 partials in either precision) judges convergence
+        if ((st = set_alpha(plan, alpha.data(), s))) return st;
+        if ((st = run(plan, PT_PLAN_OPTIMIZE, nullptr, d_brlen_inout, &p, plan->d_alpha_lnl, nullptr, nullptr,
+                      nullptr, nullptr, s)))
+            return st;
+        PT_HIP(hipMemcpyAsync(cur.data(), plan->d_alpha_lnl, sizeof(double) * B, hipMemcpyDeviceToHost, s));
+        PT_HIP(hipStreamSynchronize(s));
+        // a tree whose last round gained less than tol_lnl keeps its shape
+        bool any_active = false;
+        for (int b = 0; b < B; ++b) {
+            if (rounds > 0 && cur[b] - best[b] < o.tol_lnl) active[b] = 0;
+            any_active = any_active || active[b];
+        }
+        best = cur;
+        if (!any_active || rounds == max_rounds) break;
+        ++rounds;
+        // shapes at those lengths: Brent on log alpha, the active trees in lockstep
+        for (int b = 0; b < B; ++b) {
+            br[b].init(lo, hi, std::log(alpha[b]), tol_alpha);
+            br[b].done = !active[b];
+        }
+        for (int it = 0; it < 200; ++it) {
+            bool any = false;
+            for (int b = 0; b < B; ++b) {
+                any = any || !br[b].done;
+                trial[b] = std::exp(br[b].done ? br[b].x : br[b].point());
+            }
+            if (!any) break;
+            if ((st = set_alpha(plan, trial.data(), s))) return st;
+            if ((st = run(plan, PT_PLAN_LOGLIK, d_brlen_inout, nullptr, nullptr, plan->d_alpha_lnl, nullptr, nullptr,
+                          nullptr, nullptr, s)))
+                return st;
+            PT_HIP(hipMemcpyAsync(f.data(), plan->d_alpha_lnl, sizeof(double) * B, hipMemcpyDeviceToHost, s));
+            PT_HIP(hipStreamSynchronize(s));
+            for (int b = 0; b < B; ++b)
+                if (!br[b].done) br[b].tell(-f[b]);
+        }
+        for (int b = 0; b < B; ++b) alpha[b] = std::exp(br[b].x);
+    }
+    std::copy(best.begin(), best.end(), lnl_out);
+    std::copy(alpha.begin(), alpha.end(), alpha_inout);
+    if (rounds_out) *rounds_out = rounds;
     return PT_OK;
 }
 
