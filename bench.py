@@ -144,7 +144,8 @@ def main():
         shape = None
         with torch.cuda.stream(stream):
             if tune:
-                shape = plan.autotune(b0)
+                plan.autotune(b0)
+                shape = plan.launch_shape()
             plan.set_graphs(graphs)
             ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
                   for _ in range(steps)]
@@ -196,7 +197,7 @@ def main():
                                "(%d patterns) GTR+G4, full branch optimisation" % aln.n_patterns,
                    "topologies_per_step": NT, "precision": "fp32 partials + per-pattern scaling",
                    "launch": {"block": r32["shape"][0], "items_per_thread": r32["shape"][1],
-                              "hip_graph": True}},
+                              "blocks_per_tree": r32["shape"][2], "hip_graph": True}},
         "parity": {"max_abs_dlnl_vs_oracle": float(d32.max()), "all_within_1e-4": ok,
                    "status_converged": int(np.sum(r32["status"] == 0)),
                    "passes_mean": float(r32["passes"].mean())},
@@ -280,7 +281,8 @@ def main():
         lo = torch.zeros(T3.n_trees, dtype=torch.float64, device=dev)
         po = torch.zeros(T3.n_trees, dtype=torch.int32, device=dev)
         with torch.cuda.stream(stream):
-            shape3 = plan3o.autotune(bo0)
+            plan3o.autotune(bo0)
+            shape3 = plan3o.launch_shape()
             plan3o.set_graphs(True)
             bo.copy_(bo0, non_blocking=True)
             plan3o.optimize(bo, lo, po, stream=stream)

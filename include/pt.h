@@ -137,7 +137,9 @@ pt_status pt_batch_loglik(pt_ctx *ctx, pt_aln *const *alns, int32_t n_alns,
  * (NULL = all) selects the edges that move (partial optimisation, the
  * paper's radius option).  opt NULL = pt_opt_default(precision).
  * passes_out / status_out may be NULL; status 0 = the stopping rule was met,
- * 1 = max_passes reached first (not an error). */
+ * 1 = max_passes reached first (not an error).  PT_EINTERNAL, outputs
+ * untouched, if a tree split over several blocks (pt_plan_set_launch) had a
+ * cross-block wait time out (status 2 in the plan calls). */
 pt_status pt_batch_optimize_branches(pt_ctx *ctx, pt_aln *const *alns, int32_t n_alns,
                                      const pt_trees *trees, double *brlen_inout,
                                      const uint8_t *opt_mask, const pt_opt *opt,
@@ -177,7 +179,9 @@ pt_status pt_plan_set_graphs(pt_plan *plan, int32_t enable);
 
 /* d_brlen: device double[total edges]; d_lnl: device double[n_trees]. */
 pt_status pt_plan_loglik(pt_plan *plan, const double *d_brlen, double *d_lnl, void *stream);
-/* d_passes, d_status: device int32[n_trees] or NULL. */
+/* d_passes, d_status: device int32[n_trees] or NULL; status as in
+ * pt_batch_optimize_branches, plus 2 = a cross-block wait timed out (the
+ * tree's lnL is then NaN; see pt_plan_set_launch). */
 pt_status pt_plan_optimize(pt_plan *plan, double *d_brlen_inout, const pt_opt *opt,
                            double *d_lnl, int32_t *d_passes, int32_t *d_status,
                            void *stream);
@@ -187,10 +191,28 @@ pt_status pt_plan_grad(pt_plan *plan, const double *d_brlen, double *d_lnl,
 
 /* Time the optimisation kernel's launch shapes on this plan (lengths are
  * restored after every trial) and keep the fastest for the plan and for
- * every later plan of the same shape class in this context.  Writes the
- * chosen threads per block and items per thread to *block, *items (NULL ok). */
+ * every later plan of the same shape class in this context.  Shapes are 256
+ * or 512 threads per block, with 1 to 8 blocks per tree (see
+ * pt_plan_set_launch).  Writes the chosen threads per block and items per
+ * thread to *block, *items (NULL ok). */
 pt_status pt_plan_autotune(pt_plan *plan, const double *d_brlen, const pt_opt *opt,
                            int32_t *block, int32_t *items);
+
+/* Set the optimisation kernel's launch shape: `block` threads per block
+ * (256 or 512) and `groups` blocks per tree (1..8).  With groups = 1 a block
+ * takes one tree at a time from a work queue.  With groups > 1 each tree's
+ * patterns are split into `groups` contiguous shares, one per block, and
+ * every Newton and lnL reduction is summed across the tree's blocks, which
+ * wait for one another (bounded in time; a wait that runs out gives the
+ * tree status 2 and lnL NaN).  This is for batches too small to fill the
+ * device, and the waits need every block resident at once: it is refused
+ * (PT_EUNSUPPORTED, shape unchanged) unless n_trees * groups blocks fit
+ * on the device at the kernel's occupancy, and it assumes no other kernel
+ * holds the compute units meanwhile.  Also refused: shapes whose kernel
+ * would spill registers or whose pattern share is too large. */
+pt_status pt_plan_set_launch(pt_plan *plan, int32_t block, int32_t groups);
+/* The optimisation kernel's current shape (any pointer may be NULL). */
+pt_status pt_plan_launch_shape(const pt_plan *plan, int32_t *block, int32_t *items, int32_t *groups);
 
 /* Per-tree Gamma shapes (the paper's optional model optimisation, Methods,
  * "Phylogenetic Topographer": in its simplified case, the shape of the

@@ -24,7 +24,7 @@ EXPORTS = [
     "pt_opt_default", "pt_batch_loglik", "pt_batch_optimize_branches", "pt_batch_branch_grad",
     "pt_plan_create", "pt_plan_destroy", "pt_plan_set_graphs", "pt_plan_loglik",
     "pt_plan_optimize", "pt_plan_set_alpha", "pt_plan_optimize_alpha", "pt_plan_grad", "pt_plan_autotune",
-    "pt_plan_traffic", "pt_plan_set_profile", "pt_plan_info",
+    "pt_plan_traffic", "pt_plan_set_profile", "pt_plan_info", "pt_plan_set_launch", "pt_plan_launch_shape",
     "pt_model_info", "pt_tree_check", "pt_nni_neighbors", "pt_topology_key", "pt_topology_keys",
     "pt_nni_features", "pt_radius_masks", "pt_split_frequencies", "pt_majority_consensus",
     "pt_mlp_create", "pt_mlp_destroy", "pt_mlp_param_count", "pt_mlp_get_params", "pt_mlp_set_params",
@@ -103,6 +103,8 @@ def lib():
         L.pt_plan_loglik.argtypes = [vp, vp, vp, vp]
         L.pt_plan_optimize.argtypes = [vp, vp, P(pt_opt), vp, vp, vp, vp]
         L.pt_plan_set_alpha.argtypes = [vp, vp, vp]
+        L.pt_plan_set_launch.argtypes = [vp, i32, i32]
+        L.pt_plan_launch_shape.argtypes = [vp, P(i32), P(i32), P(i32)]
         L.pt_plan_optimize_alpha.argtypes = [vp, vp, P(pt_opt), vp, ctypes.c_double, ctypes.c_double,
                                              ctypes.c_double, i32, vp, P(i32), vp]
         L.pt_plan_grad.argtypes = [vp, vp, vp, vp, vp, vp]
@@ -490,6 +492,16 @@ class Plan:
         check(lib().pt_plan_autotune(self.h, ctypes.c_void_p(d_brlen.data_ptr()),
                                      ctypes.byref(opt) if opt else None, ctypes.byref(b), ctypes.byref(i)))
         return b.value, i.value
+
+    def set_launch(self, block, groups=1):
+        """Optimisation kernel shape: threads per block, blocks per tree."""
+        check(lib().pt_plan_set_launch(self.h, int(block), int(groups)))
+
+    def launch_shape(self):
+        """(threads per block, patterns per thread, blocks per tree)."""
+        b, i, g = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        check(lib().pt_plan_launch_shape(self.h, ctypes.byref(b), ctypes.byref(i), ctypes.byref(g)))
+        return b.value, i.value, g.value
 
     def traffic(self, kind, passes=None):
         """Algorithmic device bytes one run of `kind` moves."""

@@ -62,9 +62,9 @@ struct pt_ctx {
     int n_cu = 0;
     size_t lds_per_block = 65536;
     hipStream_t stream = nullptr;
-    // tuned threads per block of the optimisation kernel, per (precision,
-    // padded categories, largest item count)
-    std::map<std::tuple<int, int, int>, int> tuned;
+    // tuned (threads per block, blocks per tree) of the optimisation kernel,
+    // per (precision, padded categories, largest pattern count)
+    std::map<std::tuple<int, int, int>, std::pair<int, int>> tuned;
 };
 
 struct pt_aln {
@@ -91,6 +91,8 @@ struct pt_plan {
     double *d_pmat = nullptr, *d_part = nullptr, *d_scratch = nullptr;
     size_t lds_tiles = 0, lds_opt = 0;
     int opt_block = 0, opt_items = 0, opt_grid = 0, pm_doubles = 0;
+    int opt_groups = 1;                      // blocks per tree of the optimisation kernel
+    unsigned long long *d_gsync = nullptr;   // their cross-block state, per tree
     bool opt_tab_lds = true;
     void *d_tab = nullptr;
     size_t tab_bytes = 0;
@@ -210,20 +212,37 @@ constexpr size_t kOptStaticLds = 12288;
 // per thread, where the eigenbasis table lives (LDS when it fits, else a
 // per-block global buffer), dynamic LDS, grid.  Refuses shapes whose kernel
 // needs private (spill) memory.
-pt_status configure_shape(pt_plan *pl, int block) {
-    const int ni = (pl->max_P + block - 1) / block;
+// Optimisation launch shape: `block` threads per block, `groups` blocks per
+// tree.  Several blocks per tree need every block of the grid resident at
+// once (they wait for each other), so groups > 1 is refused unless
+// trees x groups blocks fit on the device at the kernel's occupancy.
+pt_status configure_shape(pt_plan *pl, int block, int groups = 1) {
+    if (groups < 1 || groups > pt::kGroupBlocksMax)
+        return fail(PT_EUNSUPPORTED, "blocks per tree must be in 1.." + std::to_string(pt::kGroupBlocksMax));
+    const bool grouped = groups > 1;
+    const int share = (pl->max_P + groups - 1) / groups;
+    const int ni = (share + block - 1) / block;
     if (!pt::optimize_shape_supported(block, ni))
         return fail(PT_EUNSUPPORTED, "patterns x padded categories too large for the optimisation kernel");
     const size_t esz = store_bytes(pl->precision);
     const size_t tab_lds = (size_t)block * ni * pl->kp * 4 * esz + (size_t)block * ni * 8;
     const size_t pm_bytes = (size_t)pl->pm_doubles * 8;
     const bool lds_ok = pm_bytes + tab_lds + kOptStaticLds <= pl->ctx->lds_per_block;
-    if (pt::optimize_spill_bytes(pl->precision, block, pl->kp, lds_ok) != 0)
+    if (pt::optimize_spill_bytes(pl->precision, block, pl->kp, lds_ok, grouped) != 0)
         return fail(PT_EUNSUPPORTED, "optimisation kernel shape needs register spills");
     const size_t lds = pm_bytes + (lds_ok ? tab_lds : 0);
-    int per_cu = pt::optimize_blocks_per_cu(pl->precision, block, pl->kp, lds_ok, lds);
+    int per_cu = pt::optimize_blocks_per_cu(pl->precision, block, pl->kp, lds_ok, grouped, lds);
     if (per_cu < 1) return fail(PT_EUNSUPPORTED, "optimisation kernel does not fit on a compute unit");
-    const int grid = (int)std::max(1L, std::min<long>(pl->n_trees, (long)per_cu * std::max(1, pl->ctx->n_cu)));
+    const long resident = (long)per_cu * std::max(1, pl->ctx->n_cu);
+    if (grouped && (long)pl->n_trees * groups > resident)
+        return fail(PT_EUNSUPPORTED, "trees x blocks per tree exceed the blocks resident at once");
+    const int grid = grouped ? pl->n_trees * groups
+                             : (int)std::max(1L, std::min<long>(pl->n_trees, resident));
+    if (grouped && !pl->d_gsync) {
+        pt_status st = dev_alloc(pl, &pl->d_gsync, sizeof(unsigned long long) * pt::kGroupSyncWords *
+                                                       (size_t)std::max(1, pl->n_trees));
+        if (st) return st;
+    }
     if (!lds_ok) {
         size_t need = (size_t)grid * tab_lds;
         if (need > pl->tab_bytes) {
@@ -238,6 +257,7 @@ pt_status configure_shape(pt_plan *pl, int block) {
     }
     pl->opt_block = block;
     pl->opt_items = ni;
+    pl->opt_groups = groups;
     pl->opt_tab_lds = lds_ok;
     pl->lds_opt = lds;
     pl->opt_grid = grid;
@@ -432,7 +452,10 @@ pt_status plan_build(pt_ctx *ctx, pt_aln *const *alns, int32_t n_alns, const pt_
     if (kinds & PT_PLAN_OPTIMIZE) {
         auto it = ctx->tuned.find(std::make_tuple(precision, pl->kp, pl->max_P));
         st = PT_EUNSUPPORTED;
-        if (it != ctx->tuned.end()) st = configure_shape(pl.get(), it->second);
+        if (it != ctx->tuned.end()) {
+            st = configure_shape(pl.get(), it->second.first, it->second.second);
+            if (st && it->second.second > 1) st = configure_shape(pl.get(), it->second.first, 1);
+        }
         // default: the widest block that needs no spills
         for (int bs : {512, 256, 1024})
             if (st) st = configure_shape(pl.get(), bs);
@@ -480,7 +503,13 @@ pt_status enqueue(pt_plan *pl, int kind, const double *brlen_c, double *brlen, c
         pt::BatchArgs a = batch_args(pl, pl->d_trees_opt, 1);
         a.tab = pl->d_tab;
         a.prof = pl->d_prof;
+        a.groups = pl->opt_groups;
+        a.gsync = pl->d_gsync;
         if ((e = pt::launch_fill_i32(pl->d_queue, 0, 1, s)) != hipSuccess) goto bad;
+        if (pl->opt_groups > 1 &&
+            (e = pt::launch_fill_i32(reinterpret_cast<int32_t *>(pl->d_gsync), 0,
+                                     (int64_t)pl->n_trees * pt::kGroupSyncWords * 2, s)) != hipSuccess)
+            goto bad;
         if ((e = pt::launch_optimize(pl->precision, pl->opt_block, pl->kp, pl->opt_items, pl->opt_tab_lds, pl->pm_doubles,
                                      pl->opt_grid, a, brlen, *op, lnl, passes, status, pl->lds_opt, s)) != hipSuccess)
             goto bad;
@@ -655,6 +684,11 @@ pt_status host_batch(pt_ctx *ctx, pt_aln *const *alns, int32_t n_alns, const pt_
             }
         }
     }
+    if (kind == PT_PLAN_OPTIMIZE)
+        for (int b = 0; b < B; ++b)
+            if (status[b] == 2)
+                return fail(PT_EINTERNAL, "tree " + std::to_string(b) + ": a cross-block wait of the "
+                                          "optimisation kernel timed out");
     std::copy(lnl.begin(), lnl.end(), lnl_out);
     if (kind == PT_PLAN_OPTIMIZE) {
         std::copy(lens_out.begin(), lens_out.end(), brlen_io);
@@ -837,14 +871,17 @@ pt_status pt_plan_autotune(pt_plan *plan, const double *d_brlen, const pt_opt *o
     hipStream_t s = plan->ctx->stream;
     double *d_lnl = nullptr;
     if ((st = dev_alloc(plan, &d_lnl, sizeof(double) * plan->n_trees))) return st;
-    int best_b = plan->opt_block;
+    int best_b = plan->opt_block, best_g = plan->opt_groups;
     float best_ms = 1e30f;
     hipEvent_t e0, e1;
     PT_HIP(hipEventCreate(&e0));
     PT_HIP(hipEventCreate(&e1));
     const size_t nb = sizeof(double) * plan->n_edges;
-    for (int bs : {256, 512, 1024}) {
-        if (configure_shape(plan, bs) != PT_OK) continue;
+    for (const auto &shape : std::vector<std::pair<int, int>>{{256, 1}, {512, 1}, {256, 2}, {512, 2}, {256, 3},
+                                                            {512, 3}, {256, 4}, {512, 4}, {256, 5}, {512, 5},
+                                                            {256, 6}, {512, 6}, {256, 8}, {512, 8}}) {
+        const int bs = shape.first, groups = shape.second;
+        if (configure_shape(plan, bs, groups) != PT_OK) continue;
         float trial = 1e30f;
         for (int rep = 0; rep < 2; ++rep) {
             PT_HIP(hipMemcpyAsync(plan->d_scratch, d_brlen, nb, hipMemcpyDeviceToDevice, s));
@@ -861,16 +898,40 @@ pt_status pt_plan_autotune(pt_plan *plan, const double *d_brlen, const pt_opt *o
         if (trial < best_ms) {
             best_ms = trial;
             best_b = bs;
+            best_g = groups;
         }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    if ((st = configure_shape(plan, best_b))) return st;
+    if ((st = configure_shape(plan, best_b, best_g))) return st;
     for (auto &kv : plan->execs) (void)hipGraphExecDestroy(kv.second);
     plan->execs.clear();
-    plan->ctx->tuned[std::make_tuple(plan->precision, plan->kp, plan->max_P)] = best_b;
+    plan->ctx->tuned[std::make_tuple(plan->precision, plan->kp, plan->max_P)] = {best_b, best_g};
     if (block) *block = plan->opt_block;
     if (items) *items = plan->opt_items;
+    return PT_OK;
+}
+
+pt_status pt_plan_set_launch(pt_plan *plan, int32_t block, int32_t groups) {
+    if (!plan || !(plan->kinds & PT_PLAN_OPTIMIZE)) return fail(PT_EINVAL, "plan was not created with PT_PLAN_OPTIMIZE");
+    if (plan->n_trees == 0) return PT_OK;
+    const int ob = plan->opt_block, og = plan->opt_groups;
+    pt_status st = configure_shape(plan, block, groups);
+    if (st) {
+        const std::string why = pt_last_error();
+        if (configure_shape(plan, ob, og) != PT_OK) return fail(PT_EINTERNAL, "could not restore the launch shape");
+        return fail(st, why);
+    }
+    for (auto &kv : plan->execs) (void)hipGraphExecDestroy(kv.second);
+    plan->execs.clear();
+    return PT_OK;
+}
+
+pt_status pt_plan_launch_shape(const pt_plan *plan, int32_t *block, int32_t *items, int32_t *groups) {
+    if (!plan) return fail(PT_EINVAL, "plan is NULL");
+    if (block) *block = plan->opt_block;
+    if (items) *items = plan->opt_items;
+    if (groups) *groups = plan->opt_groups;
     return PT_OK;
 }
 

@@ -100,7 +100,8 @@ struct TreeView {
     const double *w;     // [P]
     T *clv;              // slot 0 of this tree: [slot][Kp][P][4]
     uint16_t *cnt;       // slot 0 of this tree: [slot][P]
-    int P, K;
+    int P, K;            // P: the pattern stride of the layouts
+    int np;              // patterns this block works on (tips, w, clv, cnt start at its first)
 };
 
 template <typename T, int KP>
@@ -180,6 +181,83 @@ __device__ inline void block_sum3(double &a, double &b, double &c, double *red, 
         c += r[w * 3 + 2];
     }
     parity ^= 1;
+}
+
+// A tree optimised by G > 1 blocks, each over its own share of the patterns
+// (k_optimize): every block sum is combined across the blocks.  Thread 0 of
+// each block exchanges its triple into its own entry of one of two
+// alternating slots, counts its arrival, waits for all G arrivals of this
+// reduction, and reads the G triples back, summing them in block order, so
+// that every block holds the same totals and takes the same decisions.  All
+// of these accesses are device-scope atomics (exchanges and adds, and
+// device-scope atomic loads), coherent across the XCDs, and each is issued
+// only after the previous one returned, so no cache maintenance is needed.
+// (The blocks' own partials are a different matter: see k_optimize.)  A slot is rewritten two
+// reductions later, by when every block has read it (each block reads it
+// before arriving at the next reduction).  A wait is bounded in time: when
+// it runs out the tree is marked broken, its blocks stop waiting, and its
+// status reports the failure.
+// per-tree words (kGroupSyncWords): arrive, broken, then slots [2][G][3]
+static_assert(2 + 2 * kGroupBlocksMax * 3 <= kGroupSyncWords, "cross-block state does not fit");
+constexpr long long kGroupWaitCycles = 1ll << 27;  // shader clocks before a wait gives up
+
+__device__ inline unsigned long long load_agent(unsigned long long *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+struct GroupS {  // in LDS; thread 0 of the block alone uses the fields below G / g
+    int G, g;
+    int seq, is_broken;
+    unsigned long long *arrive, *broken, *slots;
+    double tot[3];
+};
+
+__device__ inline void group_exchange(GroupS *gs, double a, double b, double c) {
+    const int G = gs->G, s = gs->seq;
+    unsigned long long *slot = gs->slots + (size_t)(s & 1) * G * 3;
+    unsigned long long *mine = slot + gs->g * 3;
+    const unsigned long long o0 = atomicExch(mine + 0, (unsigned long long)__double_as_longlong(a));
+    const unsigned long long o1 = atomicExch(mine + 1, (unsigned long long)__double_as_longlong(b));
+    const unsigned long long o2 = atomicExch(mine + 2, (unsigned long long)__double_as_longlong(c));
+    // the arrival is issued once the three exchanges have returned
+    asm volatile("" : : "v"(o0), "v"(o1), "v"(o2) : "memory");
+    atomicAdd(gs->arrive, 1ull);
+    const unsigned long long target = (unsigned long long)G * (unsigned long long)(s + 1);
+    if (!gs->is_broken) {
+        const long long t0 = clock64();
+        while (load_agent(gs->arrive) < target) {
+            if (clock64() - t0 > kGroupWaitCycles) {
+                atomicExch(gs->broken, 1ull);
+                gs->is_broken = 1;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+    }
+    asm volatile("" : : : "memory");
+    double t0 = 0.0, t1 = 0.0, t2 = 0.0;
+    for (int h = 0; h < G; ++h) {
+        t0 += __longlong_as_double((long long)load_agent(slot + h * 3 + 0));
+        t1 += __longlong_as_double((long long)load_agent(slot + h * 3 + 1));
+        t2 += __longlong_as_double((long long)load_agent(slot + h * 3 + 2));
+    }
+    gs->tot[0] = t0;
+    gs->tot[1] = t1;
+    gs->tot[2] = t2;
+    gs->seq = s + 1;
+}
+
+// Block sum of three values, then (gs set) the sum over the tree's blocks;
+// every thread receives the totals.
+template <int BS>
+__device__ inline void group_sum3(double &a, double &b, double &c, double *red, int &parity, GroupS *gs) {
+    block_sum3<BS>(a, b, c, red, parity);
+    if (gs == nullptr) return;
+    if (threadIdx.x == 0) group_exchange(gs, a, b, c);
+    __syncthreads();
+    a = gs->tot[0];
+    b = gs->tot[1];
+    c = gs->tot[2];
 }
 
 // Per-wave table of exp(lam_m r_k t) and its first two t-derivative factors:
@@ -271,7 +349,7 @@ __device__ inline void update_sides(const TreeView<T> &v, const Op &op, int base
 #pragma unroll 1
     for (int j = 0; j < ni; ++j) {
         const int p = base + j * BS + threadIdx.x;
-        if (p >= v.P) break;
+        if (p >= v.np) break;
         Side<T, KP, TA> sa;
         Side<T, KP, TB> sb;
         sa.fetch(v, op.a, p);
@@ -359,7 +437,7 @@ __device__ inline void eval_sides(const TreeView<T> &v, int a, int b, int base, 
 #pragma unroll 1
     for (int j = 0; j < ni; ++j) {
         const int p = base + j * BS + threadIdx.x;
-        if (p >= v.P) break;
+        if (p >= v.np) break;
         Side<T, KP, TA> sa;
         Side<T, KP, TB> sb;
         sa.fetch(v, a, p);
@@ -393,7 +471,7 @@ __device__ inline void eval_sides(const TreeView<T> &v, int a, int b, int base, 
 // at length t, computed on the fly from the two sides.
 template <typename T, int BS, int KP>
 __device__ inline Sums3 eval_edge(const TreeView<T> &v, int a, int b, int base, int ni, double t, double *red,
-                                  double *wx, int parity) {
+                                  double *wx, int parity, GroupS *gs = nullptr) {
     wave_expo(wx, v.m, v.K, t);
     const double logK = log((double)v.K);
     Sums3 r;
@@ -405,7 +483,7 @@ __device__ inline Sums3 eval_edge(const TreeView<T> &v, int a, int b, int base, 
         if (b < 0) eval_sides<T, BS, KP, false, true>(v, a, b, base, ni, wx, logK, r);
         else eval_sides<T, BS, KP, false, false>(v, a, b, base, ni, wx, logK, r);
     }
-    block_sum3<BS>(r.l0, r.l1, r.l2, red, parity);
+    group_sum3<BS>(r.l0, r.l1, r.l2, red, parity, gs);
     r.parity = parity;
     return r;
 }
@@ -431,8 +509,8 @@ __device__ inline double table_sides(const TreeView<T> &v, int a, int b, int ni,
 #pragma unroll 1
     for (int j = 0; j < ni; j += kStep) {
         const int p0 = j * BS + threadIdx.x;
-        if (p0 >= v.P) break;
-        const bool two = kStep == 2 && j + 1 < ni && p0 + BS < v.P;
+        if (p0 >= v.np) break;
+        const bool two = kStep == 2 && j + 1 < ni && p0 + BS < v.np;
         const int p1 = two ? p0 + BS : p0;
         Side<T, KP, TA> sa0, sa1;
         Side<T, KP, TB> sb0, sb1;
@@ -548,7 +626,7 @@ __device__ inline void newton_rows2(const T *tab, const double *wrow, size_t row
 template <typename T, int BS, int KP>
 __device__ inline EdgeResult newton_edge(const TreeView<T> &v, int a, int b, double t, bool want_lnl,
                                          const OptParams &opt, T *tab, double *wrow, int ni, double *red,
-                                         double *wx, float *wxf, int parity) {
+                                         double *wx, float *wxf, int parity, GroupS *gs) {
     const ModelS *md = v.m;
     const size_t rows = (size_t)BS * ni;
     const double logK = log((double)v.K);
@@ -562,7 +640,7 @@ __device__ inline EdgeResult newton_edge(const TreeView<T> &v, int a, int b, dou
         else cterm = table_sides<T, BS, KP, false, false>(v, a, b, ni, rows, tab, wrow, logK);
     }
     // rows this thread owns: tid + j*BS < P
-    const int nj = v.P > (int)threadIdx.x ? min(ni, (v.P - (int)threadIdx.x + BS - 1) / BS) : 0;
+    const int nj = v.np > (int)threadIdx.x ? min(ni, (v.np - (int)threadIdx.x + BS - 1) / BS) : 0;
     const long long c1 = clock64();
     double lo = opt.t_min, hi = opt.t_max;
     int iter = 1;
@@ -585,7 +663,7 @@ __device__ inline EdgeResult newton_edge(const TreeView<T> &v, int a, int b, dou
                                     j + 1 < nj ? (j + 1) * BS + threadIdx.x : -1, (const double *)wx, v.K, false, d0,
                                     d1, d2);
         }
-        block_sum3<BS>(d0, d1, d2, red, parity);
+        group_sum3<BS>(d0, d1, d2, red, parity, gs);
         d1 -= opt.prior_rate;  // MAP: the exponential prior's log density is linear in t
         if (iter >= opt.max_newton) break;
         if (d1 > 0.0) lo = t;
@@ -615,7 +693,7 @@ __device__ inline EdgeResult newton_edge(const TreeView<T> &v, int a, int b, dou
         for (int j = 0; j < nj; j += 2)
             newton_rows2<T, KP>(tab, wrow, rows, j * BS + threadIdx.x, j + 1 < nj ? (j + 1) * BS + threadIdx.x : -1,
                                 (const double *)wx, v.K, true, l0, z1, z2);
-        block_sum3<BS>(l0, z1, z2, red, parity);
+        group_sum3<BS>(l0, z1, z2, red, parity, gs);
         lnl = l0;
     }
     EdgeResult r;
@@ -640,6 +718,7 @@ __device__ inline TreeView<T> make_view(const TreeDev &td, const AlnDev *aln, co
     v.clv = reinterpret_cast<T *>(a.clv) + td.clv_off;
     v.cnt = a.cnt + td.cnt_off;
     v.P = aln->P;
+    v.np = aln->P;
     v.K = aln->K;
     return v;
 }
@@ -786,10 +865,17 @@ __device__ inline double log_prior(const double *tl, int E, double rate) {
 // whole smoothing loop -- partial updates, per-edge Newton iterations with
 // block reductions, pass-level convergence -- without leaving the kernel.
 // Every wave exits once the counter passes the number of trees.
-// Each thread owns patterns tid + j*BS, j < ni (ni*BS >= patterns of every
-// tree).  TAB_LDS: the per-edge eigenbasis table lives in LDS after the
-// transition matrices; otherwise in a per-block slice of a.tab.
-template <typename T, int BS, int KP, bool TAB_LDS>
+// With a.groups = G > 1 (a small batch: G blocks per tree, all resident at
+// once), blocks G*q .. G*q+G-1 own tree order[q] instead, each over its own
+// contiguous share of the patterns, and every reduction spans the G blocks
+// (group_sum3); they take identical decisions, and block 0 of the group
+// writes the tree's outputs.
+// Each thread owns patterns tid + j*BS, j < ni, of its block's share
+// (ni*BS >= the share of every tree).  TAB_LDS: the per-edge eigenbasis
+// table lives in LDS after the transition matrices; otherwise in a
+// per-block slice of a.tab.  GRP: compiled for a.groups > 1 (the
+// one-block-per-tree instantiations carry none of the cross-block code).
+template <typename T, int BS, int KP, bool TAB_LDS, bool GRP>
 __global__ void __launch_bounds__(BS) k_optimize(const BatchArgs a, double *brlen, const OptParams opt, int ni,
                                                  int pm_lds_doubles, double *lnl_out, int32_t *passes_out,
                                                  int32_t *status_out) {
@@ -799,7 +885,11 @@ __global__ void __launch_bounds__(BS) k_optimize(const BatchArgs a, double *brle
     __shared__ float wxfs[(BS / 64) * kWx];
     __shared__ ModelS model;
     __shared__ int q_sh;
+    __shared__ GroupS gsh;
     const int tid = threadIdx.x;
+    const int G = GRP ? a.groups : 1;
+    const int g = GRP ? (int)(blockIdx.x % (unsigned)G) : 0;
+    GroupS *gs = GRP ? &gsh : nullptr;
     double *wx = wxs + (tid >> 6) * kWx;
     float *wxf = wxfs + (tid >> 6) * kWx;
     // per block: the table [KP][BS*ni][4] of T, then the weights [BS*ni]
@@ -808,11 +898,17 @@ __global__ void __launch_bounds__(BS) k_optimize(const BatchArgs a, double *brle
                              : reinterpret_cast<char *>(a.tab) + (size_t)blockIdx.x * (tab_bytes + (size_t)BS * ni * 8);
     T *tab = reinterpret_cast<T *>(tab_base);
     double *wrow = reinterpret_cast<double *>(tab_base + tab_bytes);
-    for (;;) {
-        if (tid == 0) q_sh = atomicAdd(a.queue, 1);
-        __syncthreads();
-        const int q = q_sh;
-        if (q >= a.n_trees) break;
+    for (int round = 0;; ++round) {
+        int q;
+        if (GRP) {
+            q = (int)(blockIdx.x / (unsigned)G);
+            if (round > 0 || q >= a.n_trees) break;
+        } else {
+            if (tid == 0) q_sh = atomicAdd(a.queue, 1);
+            __syncthreads();
+            q = q_sh;
+            if (q >= a.n_trees) break;
+        }
         const int b = a.order[q];
         const TreeDev td = a.trees[b];
         const AlnDev *aln = a.alns + td.aln;
@@ -825,6 +921,16 @@ __global__ void __launch_bounds__(BS) k_optimize(const BatchArgs a, double *brle
         float *pmf = reinterpret_cast<float *>(lds + (((size_t)E * KP * 16 + E + 1) & ~(size_t)1));
         for (int e = tid; e < E; e += BS) tl[e] = fmin(fmax(brlen[td.edge_off + e], opt.t_min), opt.t_max);
         model_to_lds(aln, &model);
+        if (GRP && tid == 0) {
+            unsigned long long *base = a.gsync + (size_t)b * kGroupSyncWords;
+            gsh.G = G;
+            gsh.g = g;
+            gsh.seq = 0;
+            gsh.is_broken = 0;
+            gsh.arrive = base;
+            gsh.broken = base + 1;
+            gsh.slots = base + 2;
+        }
         __syncthreads();
         for (int x = tid; x < E * KP * 16; x += BS) {
             const int e = x / (KP * 16), r = x % (KP * 16);
@@ -834,6 +940,14 @@ __global__ void __launch_bounds__(BS) k_optimize(const BatchArgs a, double *brle
         __syncthreads();
         TreeView<T> v = make_view<T>(td, aln, a, &model, pm);
         v.pmf = pmf;
+        // this block's share of the patterns
+        const int chunk = (v.P + G - 1) / G;
+        const int lo = min(v.P, g * chunk);
+        v.np = min(v.P - lo, chunk);
+        v.tips += lo;
+        v.w += lo;
+        v.clv += (size_t)lo * 4;
+        v.cnt += lo;
         int parity = 0;
         double prev = -INFINITY, cur = -INFINITY;
         int passes = 0;
@@ -859,14 +973,14 @@ __global__ void __launch_bounds__(BS) k_optimize(const BatchArgs a, double *brle
                 const int e = op.dst;
                 const double t0 = tl[e];
                 if (op.code == OP_EVAL) {
-                    const Sums3 r = eval_edge<T, BS, KP>(v, op.a, op.b, 0, ni, t0, red, wx, parity);
+                    const Sums3 r = eval_edge<T, BS, KP>(v, op.a, op.b, 0, ni, t0, red, wx, parity, gs);
                     parity = r.parity;
                     cur = r.l0;
                     continue;
                 }
                 // the pass's lnL comes from its last edge step (op.ea = 1)
                 const EdgeResult r =
-                    newton_edge<T, BS, KP>(v, op.a, op.b, t0, op.ea != 0, opt, tab, wrow, ni, red, wx, wxf, parity);
+                    newton_edge<T, BS, KP>(v, op.a, op.b, t0, op.ea != 0, opt, tab, wrow, ni, red, wx, wxf, parity, gs);
                 parity = r.parity;
                 if (op.ea) cur = r.lnl;
                 pc[PROF_EDGE_STEPS] += 1;
@@ -893,6 +1007,17 @@ __global__ void __launch_bounds__(BS) k_optimize(const BatchArgs a, double *brle
             if (passes >= opt.max_passes) break;
             prev = cur;
         }
+        if (GRP && kF32 && td.n_final > 0) {
+            // The FP64 pass below reuses the tree's buffer in another layout,
+            // so a block writes bytes that another block wrote as FP32
+            // partials.  The XCDs' L2 caches are not coherent: a dirty FP32
+            // line left in another XCD's L2 could later be written back over
+            // the new FP64 values.  Every wave writes back its L2 (release at
+            // device scope) and the group meets once before any FP64 write.
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            double z0 = 0.0, z1 = 0.0, z2 = 0.0;
+            group_sum3<BS>(z0, z1, z2, red, parity, gs);
+        }
         if (std::is_same<T, float>::value && td.n_final > 0) {
             // Report lnL from FP64 partials at the final lengths: one post-order
             // pass over the same buffer (dense slots; the FP32 partials are no
@@ -902,31 +1027,40 @@ __global__ void __launch_bounds__(BS) k_optimize(const BatchArgs a, double *brle
             vd.pm = v.pm;
             vd.tips = v.tips;
             vd.w = v.w;
-            vd.clv = reinterpret_cast<double *>(v.clv);
+            // the same share in the FP64 layout: every block of the tree has
+            // finished reading FP32 partials (their reads preceded the
+            // arrivals at the last reduction)
+            vd.clv = reinterpret_cast<double *>(reinterpret_cast<T *>(a.clv) + td.clv_off) + (size_t)lo * 4;
             vd.cnt = v.cnt;
             vd.P = v.P;
+            vd.np = v.np;
             vd.K = v.K;
             for (int o = 0; o < td.n_final; ++o) {
                 const Op op = a.ops[td.op_final + o];
                 if (op.code == OP_UPDATE) {
                     do_update<double, BS, KP>(vd, op, 0, ni);
                 } else {
-                    const Sums3 r = eval_edge<double, BS, KP>(vd, op.a, op.b, 0, ni, tl[op.dst], red, wx, parity);
+                    const Sums3 r =
+                        eval_edge<double, BS, KP>(vd, op.a, op.b, 0, ni, tl[op.dst], red, wx, parity, gs);
                     parity = r.parity;
                     cur = r.l0 + log_prior(tl, E, opt.prior_rate);
                 }
             }
         }
-        for (int e = tid; e < E; e += BS) brlen[td.edge_off + e] = tl[e];
-        if (tid == 0 && a.prof) {
-            pc[PROF_PASSES] = passes;
-            pc[PROF_CYC_TOTAL] = clock64() - t_start;
-            for (int f = 0; f < PROF_FIELDS; ++f) a.prof[(size_t)b * PROF_FIELDS + f] = pc[f];
-        }
-        if (tid == 0) {
-            lnl_out[b] = cur;
-            if (passes_out) passes_out[b] = passes;
-            if (status_out) status_out[b] = converged ? 0 : 1;
+        if (g == 0) {
+            for (int e = tid; e < E; e += BS) brlen[td.edge_off + e] = tl[e];
+            if (tid == 0 && a.prof) {
+                pc[PROF_PASSES] = passes;
+                pc[PROF_CYC_TOTAL] = clock64() - t_start;
+                for (int f = 0; f < PROF_FIELDS; ++f) a.prof[(size_t)b * PROF_FIELDS + f] = pc[f];
+            }
+            if (tid == 0) {
+                // a timed-out wait anywhere in the group: status 2, lnL NaN
+                const bool broken = GRP && load_agent(gsh.broken) != 0ull;
+                lnl_out[b] = broken ? NAN : cur;
+                if (passes_out) passes_out[b] = passes;
+                if (status_out) status_out[b] = broken ? 2 : (converged ? 0 : 1);
+            }
         }
         __syncthreads();
     }
@@ -934,49 +1068,52 @@ __global__ void __launch_bounds__(BS) k_optimize(const BatchArgs a, double *brle
 
 // ------------------------------------------------------------- dispatch
 
-template <typename T, int BS, int KP, bool L>
+template <typename T, int BS, int KP, bool L, bool GRP>
 hipError_t launch_opt_t(int grid, const BatchArgs &a, double *brlen, const OptParams &opt, int ni, int pm_doubles,
                         double *lnl, int32_t *passes, int32_t *status, size_t lds, hipStream_t s) {
     if (lds > 65536) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_optimize<T, BS, KP, L>),
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_optimize<T, BS, KP, L, GRP>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL((k_optimize<T, BS, KP, L>), dim3(grid), dim3(BS), lds, s, a, brlen, opt, ni, pm_doubles,
-                       lnl, passes, status);
+    hipLaunchKernelGGL((k_optimize<T, BS, KP, L, GRP>), dim3(grid), dim3(BS), lds, s, a, brlen, opt, ni,
+                       pm_doubles, lnl, passes, status);
     return hipGetLastError();
 }
 
-template <typename T, int BS, int KP, bool L>
+template <typename T, int BS, int KP, bool L, bool GRP>
 int occ_opt_t(size_t lds) {
     int n = 0;
-    if (lds > 65536 && hipFuncSetAttribute(reinterpret_cast<const void *>(k_optimize<T, BS, KP, L>),
+    if (lds > 65536 && hipFuncSetAttribute(reinterpret_cast<const void *>(k_optimize<T, BS, KP, L, GRP>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
         return 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_optimize<T, BS, KP, L>, BS, lds) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_optimize<T, BS, KP, L, GRP>, BS, lds) != hipSuccess)
+        return 0;
     return n;
 }
 
-template <typename T, int BS, int KP, bool L>
+template <typename T, int BS, int KP, bool L, bool GRP>
 size_t spill_opt_t() {
     hipFuncAttributes at;
-    if (hipFuncGetAttributes(&at, reinterpret_cast<const void *>(k_optimize<T, BS, KP, L>)) != hipSuccess)
+    if (hipFuncGetAttributes(&at, reinterpret_cast<const void *>(k_optimize<T, BS, KP, L, GRP>)) != hipSuccess)
         return ~size_t(0);
     return at.localSizeBytes;
 }
 
-// Runtime (precision, block, padded categories, table placement) to the
-// matching instantiation of FN.
-#define PT_OPT_CALL(FN, ...)                                                                 \
-    do {                                                                                     \
-        if (block == 256 && precision == PT_FP32)                                            \
-            return tab_lds ? FN<float, 256, KP, true>(__VA_ARGS__) : FN<float, 256, KP, false>(__VA_ARGS__); \
-        if (block == 256)                                                                    \
-            return tab_lds ? FN<double, 256, KP, true>(__VA_ARGS__) : FN<double, 256, KP, false>(__VA_ARGS__); \
-        if (block == 512 && precision == PT_FP32)                                            \
-            return tab_lds ? FN<float, 512, KP, true>(__VA_ARGS__) : FN<float, 512, KP, false>(__VA_ARGS__); \
-        if (block == 512)                                                                    \
-            return tab_lds ? FN<double, 512, KP, true>(__VA_ARGS__) : FN<double, 512, KP, false>(__VA_ARGS__); \
+// Runtime (precision, block, padded categories, table placement, grouped)
+// to the matching instantiation of FN.
+#define PT_OPT_CALL_T(FN, T, BSZ, ...)                                                        \
+    do {                                                                                      \
+        if (grouped)                                                                          \
+            return tab_lds ? FN<T, BSZ, KP, true, true>(__VA_ARGS__) : FN<T, BSZ, KP, false, true>(__VA_ARGS__); \
+        return tab_lds ? FN<T, BSZ, KP, true, false>(__VA_ARGS__) : FN<T, BSZ, KP, false, false>(__VA_ARGS__); \
+    } while (0)
+#define PT_OPT_CALL(FN, ...)                                                                  \
+    do {                                                                                      \
+        if (block == 256 && precision == PT_FP32) PT_OPT_CALL_T(FN, float, 256, __VA_ARGS__);  \
+        if (block == 256) PT_OPT_CALL_T(FN, double, 256, __VA_ARGS__);                        \
+        if (block == 512 && precision == PT_FP32) PT_OPT_CALL_T(FN, float, 512, __VA_ARGS__);  \
+        if (block == 512) PT_OPT_CALL_T(FN, double, 512, __VA_ARGS__);                        \
     } while (0)
 
 #define PT_KP_SWITCH(...)                                   \
@@ -1009,12 +1146,12 @@ bool optimize_shape_supported(int block, int items) {
     return (block == 256 || block == 512) && items >= 1 && items <= 64;
 }
 
-int optimize_blocks_per_cu(int precision, int block, int kp, bool tab_lds, size_t lds) {
+int optimize_blocks_per_cu(int precision, int block, int kp, bool tab_lds, bool grouped, size_t lds) {
     PT_KP_SWITCH(PT_OPT_CALL(occ_opt_t, lds));
     return 0;
 }
 
-size_t optimize_spill_bytes(int precision, int block, int kp, bool tab_lds) {
+size_t optimize_spill_bytes(int precision, int block, int kp, bool tab_lds, bool grouped) {
     PT_KP_SWITCH(PT_OPT_CALL(spill_opt_t));
     return ~size_t(0);
 }
@@ -1022,6 +1159,7 @@ size_t optimize_spill_bytes(int precision, int block, int kp, bool tab_lds) {
 hipError_t launch_optimize(int precision, int block, int kp, int items, bool tab_lds, int pm_doubles, int grid,
                            const BatchArgs &a, double *brlen, const OptParams &opt, double *lnl, int32_t *passes,
                            int32_t *status, size_t lds, hipStream_t s) {
+    const bool grouped = a.groups > 1;
     PT_KP_SWITCH(PT_OPT_CALL(launch_opt_t, grid, a, brlen, opt, items, pm_doubles, lnl, passes, status, lds, s));
     return hipErrorInvalidValue;
 }

@@ -26,7 +26,14 @@ struct BatchArgs {
     int32_t part_cols;
     int32_t kp;                 // padded category count of every layout in the batch
     long long *prof;            // optimisation: per-tree phase counters [n_trees][8], or null
+    int32_t groups;             // optimisation: blocks per tree (1: one block per tree, work queue)
+    unsigned long long *gsync;  // optimisation with groups > 1: per-tree cross-block words, zeroed
 };
+
+// Optimisation with several blocks per tree: at most kGroupBlocksMax blocks,
+// and kGroupSyncWords words of cross-block state per tree.
+constexpr int kGroupBlocksMax = 8;
+constexpr int kGroupSyncWords = 64;
 
 // Per-tree optimisation counters (when BatchArgs::prof is set).
 enum : int { PROF_PASSES, PROF_EDGE_STEPS, PROF_NEWTON_ITERS, PROF_UPDATES, PROF_CYC_UPDATE,
@@ -37,11 +44,12 @@ constexpr int kTileBlock = 256;
 constexpr int kTileItems = 1;
 
 // Optimisation kernel shapes: threads per block 256 or 512, patterns per
-// thread 1..64 (a runtime loop bound); kp = padded categories 1, 2, 4, 8.
+// thread 1..64 (a runtime loop bound); kp = padded categories 1, 2, 4, 8;
+// grouped: the instantiation for several blocks per tree.
 bool optimize_shape_supported(int block, int items);
-int optimize_blocks_per_cu(int precision, int block, int kp, bool tab_lds, size_t lds_bytes);
+int optimize_blocks_per_cu(int precision, int block, int kp, bool tab_lds, bool grouped, size_t lds_bytes);
 // Private (spill) bytes per thread of an optimisation kernel instantiation.
-size_t optimize_spill_bytes(int precision, int block, int kp, bool tab_lds);
+size_t optimize_spill_bytes(int precision, int block, int kp, bool tab_lds, bool grouped);
 
 hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
 hipError_t launch_pmat(const BatchArgs &a, const double *brlen, hipStream_t s);
@@ -50,6 +58,7 @@ hipError_t launch_tiles(int precision, int kp, const BatchArgs &a, const double 
                         hipStream_t s);
 hipError_t launch_reduce(bool grad, const BatchArgs &a, double *lnl, double *grad_out,
                          double *hess_out, hipStream_t s);
+// With a.groups > 1, grid = trees x groups and a.gsync zeroed beforehand.
 hipError_t launch_optimize(int precision, int block, int kp, int items, bool tab_lds, int pm_doubles, int grid,
                            const BatchArgs &a, double *brlen, const OptParams &opt, double *lnl,
                            int32_t *passes, int32_t *status, size_t lds_bytes, hipStream_t s);
