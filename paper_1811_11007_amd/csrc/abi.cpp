@@ -234,10 +234,13 @@ pt_status configure_shape(pt_plan *pl, int block, int groups = 1) {
     int per_cu = pt::optimize_blocks_per_cu(pl->precision, block, pl->kp, lds_ok, grouped, lds);
     if (per_cu < 1) return fail(PT_EUNSUPPORTED, "optimisation kernel does not fit on a compute unit");
     const long resident = (long)per_cu * std::max(1, pl->ctx->n_cu);
-    if (grouped && (long)pl->n_trees * groups > resident)
+    // grouped: whole trees per XCD (the kernel's block-to-tree mapping), so
+    // the grid rounds the trees up to a multiple of the XCD count and each
+    // XCD must hold its share
+    const long grouped_grid = (long)pt::kXcds * groups * ((pl->n_trees + pt::kXcds - 1) / pt::kXcds);
+    if (grouped && grouped_grid > resident)
         return fail(PT_EUNSUPPORTED, "trees x blocks per tree exceed the blocks resident at once");
-    const int grid = grouped ? pl->n_trees * groups
-                             : (int)std::max(1L, std::min<long>(pl->n_trees, resident));
+    const int grid = grouped ? (int)grouped_grid : (int)std::max(1L, std::min<long>(pl->n_trees, resident));
     if (grouped && !pl->d_gsync) {
         pt_status st = dev_alloc(pl, &pl->d_gsync, sizeof(unsigned long long) * pt::kGroupSyncWords *
                                                        (size_t)std::max(1, pl->n_trees));

@@ -866,8 +866,8 @@ __device__ inline double log_prior(const double *tl, int E, double rate) {
 // block reductions, pass-level convergence -- without leaving the kernel.
 // Every wave exits once the counter passes the number of trees.
 // With a.groups = G > 1 (a small batch: G blocks per tree, all resident at
-// once), blocks G*q .. G*q+G-1 own tree order[q] instead, each over its own
-// contiguous share of the patterns, and every reduction spans the G blocks
+// once), G blocks on one XCD own tree order[q] instead (see below), each
+// over its own contiguous share of the patterns, and every reduction spans the G blocks
 // (group_sum3); they take identical decisions, and block 0 of the group
 // writes the tree's outputs.
 // Each thread owns patterns tid + j*BS, j < ni, of its block's share
@@ -888,7 +888,12 @@ __global__ void __launch_bounds__(BS) k_optimize(const BatchArgs a, double *brle
     __shared__ GroupS gsh;
     const int tid = threadIdx.x;
     const int G = GRP ? a.groups : 1;
-    const int g = GRP ? (int)(blockIdx.x % (unsigned)G) : 0;
+    // grouped: the hardware deals blocks to the XCDs in turn, so block i
+    // runs on XCD i % kXcds; the G blocks of a tree are taken from one XCD
+    // (trees x, x + kXcds, ... on XCD x), keeping their cross-block traffic
+    // within one L2
+    const unsigned xcd = blockIdx.x % (unsigned)kXcds, xslot = blockIdx.x / (unsigned)kXcds;
+    const int g = GRP ? (int)(xslot % (unsigned)G) : 0;
     GroupS *gs = GRP ? &gsh : nullptr;
     double *wx = wxs + (tid >> 6) * kWx;
     float *wxf = wxfs + (tid >> 6) * kWx;
@@ -901,7 +906,7 @@ __global__ void __launch_bounds__(BS) k_optimize(const BatchArgs a, double *brle
     for (int round = 0;; ++round) {
         int q;
         if (GRP) {
-            q = (int)(blockIdx.x / (unsigned)G);
+            q = (int)((xslot / (unsigned)G) * (unsigned)kXcds + xcd);
             if (round > 0 || q >= a.n_trees) break;
         } else {
             if (tid == 0) q_sh = atomicAdd(a.queue, 1);

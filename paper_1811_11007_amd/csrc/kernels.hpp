@@ -34,6 +34,9 @@ struct BatchArgs {
 // and kGroupSyncWords words of cross-block state per tree.
 constexpr int kGroupBlocksMax = 8;
 constexpr int kGroupSyncWords = 64;
+// XCDs of the device, to which consecutive blocks are dealt in turn; a
+// grouped launch has kXcds * groups * ceil(trees / kXcds) blocks.
+constexpr int kXcds = 8;
 
 // Per-tree optimisation counters (when BatchArgs::prof is set).
 enum : int { PROF_PASSES, PROF_EDGE_STEPS, PROF_NEWTON_ITERS, PROF_UPDATES, PROF_CYC_UPDATE,
