@@ -209,7 +209,10 @@ pt_status pt_plan_autotune(pt_plan *plan, const double *d_brlen, const pt_opt *o
  * (PT_EUNSUPPORTED, shape unchanged) unless n_trees * groups blocks fit
  * on the device at the kernel's occupancy, and it assumes no other kernel
  * holds the compute units meanwhile.  Also refused: shapes whose kernel
- * would spill registers or whose pattern share is too large. */
+ * would spill registers or whose pattern share is too large.  A new plan
+ * uses the shape its context's autotuner last chose for plans of its kind,
+ * else, when it has at most half as many trees as the device has compute
+ * units, 256 threads and up to 4 blocks per tree, else one block per tree. */
 pt_status pt_plan_set_launch(pt_plan *plan, int32_t block, int32_t groups);
 /* The optimisation kernel's current shape (any pointer may be NULL). */
 pt_status pt_plan_launch_shape(const pt_plan *plan, int32_t *block, int32_t *items, int32_t *groups);

@@ -459,8 +459,13 @@ pt_status plan_build(pt_ctx *ctx, pt_aln *const *alns, int32_t n_alns, const pt_
             st = configure_shape(pl.get(), it->second.first, it->second.second);
             if (st && it->second.second > 1) st = configure_shape(pl.get(), it->second.first, 1);
         }
-        // default: the widest block that needs no spills
-        for (int bs : {512, 256, 1024})
+        // default: a batch that leaves at least half the compute units idle
+        // splits each tree over up to 4 blocks of 256 threads (the fastest
+        // shape measured on such batches), if they fit at once; otherwise
+        // the widest block that needs no spills
+        const int n_cu = std::max(1, ctx->n_cu);
+        if (st && B > 0 && 2 * B <= n_cu) st = configure_shape(pl.get(), 256, std::min(4, n_cu / B));
+        for (int bs : {512, 256})
             if (st) st = configure_shape(pl.get(), bs);
         if (st) return st;
     }
