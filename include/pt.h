@@ -100,8 +100,9 @@ typedef struct {
 /* Branch-length optimisation settings.  Per edge: safeguarded Newton on
  * t in [t_min, t_max], at most max_newton derivative evaluations, stopping
  * when a step would move t by at most tol_newton * max(t, 1e-6) (not taken),
- * or after taking a Newton step of at most sqrt(tol_newton) * max(t, 1e-6)
- * (quadratic convergence leaves an error of order tol_newton).  Per tree:
+ * or after taking a Newton step of at most max(sqrt(tol_newton), 0.03) *
+ * max(t, 1e-6) (quadratic convergence; the next pass revisits the edge, and
+ * the per-tree rule below bounds the final accuracy).  Per tree:
  * passes over the masked edges until a pass raises the objective by less
  * than tol_lnl and changes no length by more than tol_t relative, or
  * max_passes.

@@ -605,6 +605,12 @@ __device__ inline void newton_rows2(const T *tab, const double *wrow, size_t row
     }
 }
 
+// Relative Newton step below which an edge's iterations end without a
+// confirming evaluation (see newton_edge).  Measured on the 48 C2
+// neighbours: 1.46 -> 1.07 iterations per edge step (FP32 partials) and
+// 1.70 -> 1.04 (FP64), for at most one more pass on a few trees.
+constexpr double kNewtonAccept = 0.03;
+
 // OP_NEWTON: safeguarded, projected Newton on the length of one edge, for
 // lnL(t) - prior_rate * t (prior_rate 0: maximum likelihood).
 //  - the eigenbasis coefficients of this thread's patterns are computed once
@@ -618,8 +624,9 @@ __device__ inline void newton_rows2(const T *tab, const double *wrow, size_t row
 //    geometrically;
 //  - a bound with the derivative pointing outwards is an optimum;
 //  - a step of at most tol * max(t, 1e-6) is converged and not taken; a
-//    Newton step of at most sqrt(tol) * max(t, 1e-6) is taken and ends the
-//    edge (quadratic convergence leaves an error of order tol);
+//    Newton step of at most max(sqrt(tol), kNewtonAccept) * max(t, 1e-6) is
+//    taken and ends the edge (quadratic convergence; the next pass revisits
+//    the edge);
 //  - with want_lnl, lnL is evaluated at the returned t.
 // All threads hold identical block totals, so every thread takes the same
 // decisions.
@@ -680,10 +687,12 @@ __device__ inline EdgeResult newton_edge(const TreeView<T> &v, int a, int b, dou
         if (dt <= opt.tol_newton * scale) break;
         t = tn;
         // Newton converges quadratically near the optimum: after a Newton
-        // step of relative size below sqrt(tol_newton) the remaining error is
-        // of order tol_newton, so the step is taken without a confirming
-        // evaluation.
-        if (inside && dt <= sqrt(opt.tol_newton) * scale) break;
+        // step of relative size d the remaining error is of order d^2, so a
+        // step of at most kNewtonAccept (or sqrt(tol_newton)) relative is
+        // taken without a confirming evaluation.  The next pass revisits the
+        // edge, and the pass-level rule (no step above tol_t) bounds the
+        // final accuracy.
+        if (inside && dt <= fmax(sqrt(opt.tol_newton), kNewtonAccept) * scale) break;
     }
     double lnl = 0.0;
     if (want_lnl) {
