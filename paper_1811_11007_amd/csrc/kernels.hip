@@ -43,6 +43,7 @@ struct Store<float> {
     __device__ static inline void widen(const Raw &v, double x[4]) {
         x[0] = v.x; x[1] = v.y; x[2] = v.z; x[3] = v.w;
     }
+    __device__ static inline double as_stored(double x) { return (double)(float)x; }
     __device__ static inline void store(float *p, const double x[4]) {
         *reinterpret_cast<float4 *>(p) =
             make_float4((float)x[0], (float)x[1], (float)x[2], (float)x[3]);
@@ -64,6 +65,7 @@ struct Store<double> {
     __device__ static inline void widen(const Raw &v, double x[4]) {
         x[0] = v.a.x; x[1] = v.a.y; x[2] = v.b.x; x[3] = v.b.y;
     }
+    __device__ static inline double as_stored(double x) { return x; }
     __device__ static inline void store(double *p, const double x[4]) {
         reinterpret_cast<double2 *>(p)[0] = make_double2(x[0], x[1]);
         reinterpret_cast<double2 *>(p)[1] = make_double2(x[2], x[3]);
@@ -496,10 +498,13 @@ struct EdgeResult {
 
 // The eigenbasis table of an edge whose sides are of kinds TA / TB: this
 // thread's rows of tab ([k][row][4]) and wrow; returns the sum of its rows'
-// t-independent lnL terms.
-template <typename T, int BS, int KP, bool TA, bool TB>
+// t-independent lnL terms.  FUSE: also adds the rows' terms of the first
+// Newton iteration, at the exponentials wxe, to f1 and f2, from the values as
+// stored and in the order of newton_rows2, so the sums are the ones a row
+// pass over the finished table would give.
+template <typename T, int BS, int KP, bool TA, bool TB, bool FUSE, typename X>
 __device__ inline double table_sides(const TreeView<T> &v, int a, int b, int ni, size_t rows, T *tab, double *wrow,
-                                     double logK) {
+                                     double logK, const X *wxe, double &f1, double &f2) {
     const ModelS *md = v.m;
     double cterm = 0.0;
     // two patterns per step (FP32 partials; with FP64 the registers of a
@@ -521,6 +526,7 @@ __device__ inline double table_sides(const TreeView<T> &v, int a, int b, int ni,
         const double w0 = ldg(v.w + p0), w1 = ldg(v.w + p1);
         cterm += w0 * const_term<T>(sa0.c + sb0.c, logK);
         wrow[p0] = w0;
+        double L = 0.0, L1 = 0.0, L2 = 0.0;
 #pragma unroll
         for (int k = 0; k < KP; ++k) {
             if (k < v.K) {
@@ -529,11 +535,27 @@ __device__ inline double table_sides(const TreeView<T> &v, int a, int b, int ni,
                 sb0.get(k, xb);
                 coeffs_x(md, xa, xb, sk);
                 Store<T>::store(tab + ((size_t)k * rows + p0) * 4, sk);
+                if constexpr (FUSE) {
+#pragma unroll
+                    for (int m = 0; m < 4; ++m) {
+                        const double q = Store<T>::as_stored(sk[m]);
+                        L += q * (double)wxe[k * 4 + m];
+                        L1 += q * (double)wxe[4 * kMaxCats + k * 4 + m];
+                        L2 += q * (double)wxe[8 * kMaxCats + k * 4 + m];
+                    }
+                }
             }
+        }
+        if constexpr (FUSE) {
+            const double ia = recip(L);
+            const double r1 = L1 * ia;
+            f1 += w0 * r1;
+            f2 += w0 * (L2 * ia - r1 * r1);
         }
         if (two) {
             cterm += w1 * const_term<T>(sa1.c + sb1.c, logK);
             wrow[p1] = w1;
+            double M = 0.0, M1 = 0.0, M2 = 0.0;
 #pragma unroll
             for (int k = 0; k < KP; ++k) {
                 if (k < v.K) {
@@ -542,7 +564,22 @@ __device__ inline double table_sides(const TreeView<T> &v, int a, int b, int ni,
                     sb1.get(k, xb);
                     coeffs_x(md, xa, xb, sk);
                     Store<T>::store(tab + ((size_t)k * rows + p1) * 4, sk);
+                    if constexpr (FUSE) {
+#pragma unroll
+                        for (int m = 0; m < 4; ++m) {
+                            const double q = Store<T>::as_stored(sk[m]);
+                            M += q * (double)wxe[k * 4 + m];
+                            M1 += q * (double)wxe[4 * kMaxCats + k * 4 + m];
+                            M2 += q * (double)wxe[8 * kMaxCats + k * 4 + m];
+                        }
+                    }
                 }
+            }
+            if constexpr (FUSE) {
+                const double ib = recip(M);
+                const double r1 = M1 * ib;
+                f1 += w1 * r1;
+                f2 += w1 * (M2 * ib - r1 * r1);
             }
         }
     }
@@ -616,7 +653,9 @@ constexpr double kNewtonAccept = 0.03;
 //  - the eigenbasis coefficients of this thread's patterns are computed once
 //    into `tab` (layout [k][row][4], rows = BS*ni pattern slots) and the
 //    pattern weights into `wrow` (in LDS, or in a per-block global buffer),
-//    then every iteration is a pass over them plus one block sum;
+//    then every iteration is a pass over them plus one block sum (up to four
+//    padded categories, the first iteration's terms are summed while the
+//    table is built);
 //  - the bracket (lo, hi) starts as [t_min, t_max] and shrinks to t on the
 //    side the first derivative points away from;
 //  - a Newton step is taken when d2 < 0 and it stays in the bracket (the
@@ -638,13 +677,24 @@ __device__ inline EdgeResult newton_edge(const TreeView<T> &v, int a, int b, dou
     const size_t rows = (size_t)BS * ni;
     const double logK = log((double)v.K);
     const long long c0 = clock64();
+    // the first iteration's derivative terms are summed while the table is
+    // built (with the same rounding and order as the row passes below)
+    constexpr bool kF = std::is_same<T, float>::value;
+    constexpr bool kFuse = KP <= 4;  // with eight categories the extra registers would spill
+    using XE = typename std::conditional<kF, float, double>::type;
+    if constexpr (kFuse) {
+        if constexpr (kF) wave_expo(wx, v.m, v.K, t, wxf);
+        else wave_expo(wx, v.m, v.K, t);
+    }
+    const XE *wxe = kF ? reinterpret_cast<const XE *>(wxf) : reinterpret_cast<const XE *>(wx);
+    double f1 = 0.0, f2 = 0.0;
     double cterm;
     if (a < 0) {
-        if (b < 0) cterm = table_sides<T, BS, KP, true, true>(v, a, b, ni, rows, tab, wrow, logK);
-        else cterm = table_sides<T, BS, KP, true, false>(v, a, b, ni, rows, tab, wrow, logK);
+        if (b < 0) cterm = table_sides<T, BS, KP, true, true, kFuse>(v, a, b, ni, rows, tab, wrow, logK, wxe, f1, f2);
+        else cterm = table_sides<T, BS, KP, true, false, kFuse>(v, a, b, ni, rows, tab, wrow, logK, wxe, f1, f2);
     } else {
-        if (b < 0) cterm = table_sides<T, BS, KP, false, true>(v, a, b, ni, rows, tab, wrow, logK);
-        else cterm = table_sides<T, BS, KP, false, false>(v, a, b, ni, rows, tab, wrow, logK);
+        if (b < 0) cterm = table_sides<T, BS, KP, false, true, kFuse>(v, a, b, ni, rows, tab, wrow, logK, wxe, f1, f2);
+        else cterm = table_sides<T, BS, KP, false, false, kFuse>(v, a, b, ni, rows, tab, wrow, logK, wxe, f1, f2);
     }
     // rows this thread owns: tid + j*BS < P
     const int nj = v.np > (int)threadIdx.x ? min(ni, (v.np - (int)threadIdx.x + BS - 1) / BS) : 0;
@@ -653,7 +703,10 @@ __device__ inline EdgeResult newton_edge(const TreeView<T> &v, int a, int b, dou
     int iter = 1;
     for (;; ++iter) {
         double d0 = 0.0, d1 = 0.0, d2 = 0.0;
-        if constexpr (std::is_same<T, float>::value) {
+        if (kFuse && iter == 1) {
+            d1 = f1;
+            d2 = f2;
+        } else if constexpr (std::is_same<T, float>::value) {
             // FP32 partials: FP32 exponentials suffice for the derivatives
             // (they only steer Newton); lnL below uses FP64 ones
             wave_expo(wx, v.m, v.K, t, wxf);
