@@ -57,7 +57,11 @@ const char *pt_last_error(void);
 /* A context owns one device's stream, memory and tuning table.  Limits:
  * device index as seen by HIP.  The environment variable PT_ARENA_CAP_BYTES
  * (decimal) caps the device bytes one batch may use; host-pointer batch calls
- * split a batch that exceeds it into smaller batches with identical results. */
+ * split a batch that exceeds it into smaller batches with identical results.
+ * Device memory of destroyed plans stays with the context for later plans
+ * (a new plan takes a kept block of one to two times the size it needs), up
+ * to PT_POOL_CAP_BYTES (decimal, default 64 GiB); a failing allocation first
+ * returns the kept blocks to the device.  pt_ctx_destroy frees them. */
 typedef struct pt_ctx pt_ctx;
 pt_status pt_ctx_create(int32_t device, pt_ctx **out);
 void pt_ctx_destroy(pt_ctx *ctx);
@@ -175,6 +179,8 @@ typedef struct pt_plan pt_plan;
 pt_status pt_plan_create(pt_ctx *ctx, pt_aln *const *alns, int32_t n_alns,
                          const pt_trees *trees, const uint8_t *opt_mask,
                          int32_t precision, int32_t kinds, pt_plan **out);
+/* Waits for the device to finish, then gives the plan's device memory back
+ * to its context (see pt_ctx_create). */
 void pt_plan_destroy(pt_plan *plan);
 pt_status pt_plan_set_graphs(pt_plan *plan, int32_t enable);
 

@@ -65,6 +65,12 @@ struct pt_ctx {
     // tuned (threads per block, blocks per tree) of the optimisation kernel,
     // per (precision, padded categories, largest pattern count)
     std::map<std::tuple<int, int, int>, std::pair<int, int>> tuned;
+    // device blocks of destroyed plans, kept for later plans (size -> block):
+    // a search creates a plan of the same size for every batch, and a fresh
+    // hipMalloc / hipFree of tens of GB each time cost far more than the
+    // optimisation itself
+    std::multimap<size_t, void *> pool;
+    size_t pool_bytes = 0;
 };
 
 struct pt_aln {
@@ -100,7 +106,7 @@ struct pt_plan {
     int64_t device_bytes = 0;
     bool graphs = false;
     std::map<std::vector<uint64_t>, hipGraphExec_t> execs;
-    std::vector<void *> allocs;
+    std::vector<std::pair<void *, size_t>> allocs;  // device blocks and their sizes
     // host copies for traffic accounting
     std::vector<Op> ops_h;
     std::vector<TreeDev> tll_h, tgr_h, top_h;
@@ -111,22 +117,73 @@ struct pt_plan {
 
 namespace {
 
+// Bytes the context keeps in its pool of released device blocks
+// (PT_POOL_CAP_BYTES, default 64 GiB); beyond it the largest are freed.
+size_t pool_cap() {
+    const char *s = std::getenv("PT_POOL_CAP_BYTES");
+    if (s && *s) {
+        char *end = nullptr;
+        long long v = std::strtoll(s, &end, 10);
+        if (end && *end == 0 && v >= 0) return (size_t)v;
+    }
+    return (size_t)64 << 30;
+}
+
+void pool_trim(pt_ctx *ctx, size_t cap) {
+    while (ctx->pool_bytes > cap && !ctx->pool.empty()) {
+        auto it = std::prev(ctx->pool.end());
+        (void)hipFree(it->second);
+        ctx->pool_bytes -= it->first;
+        ctx->pool.erase(it);
+    }
+}
+
+// A device block for a plan: the smallest pooled block of 1x to 2x the size,
+// else a new one (after emptying the pool if the device is full).  Plans
+// initialise everything they read, so a reused block needs no clearing.
 template <typename P>
 pt_status dev_alloc(pt_plan *pl, P **out, size_t bytes) {
+    pt_ctx *ctx = pl->ctx;
+    bytes = std::max<size_t>(bytes, 16);
+    bytes = (bytes + 255) & ~(size_t)255;
     void *p = nullptr;
-    if (bytes == 0) bytes = 16;
-    hipError_t e = hipMalloc(&p, bytes);
-    if (e != hipSuccess) return fail(PT_ENOMEM, "hipMalloc(" + std::to_string(bytes) + "): " + hipGetErrorString(e));
-    pl->allocs.push_back(p);
-    pl->device_bytes += (int64_t)bytes;
+    size_t got = bytes;
+    auto it = ctx->pool.lower_bound(bytes);
+    if (it != ctx->pool.end() && it->first <= 2 * bytes) {
+        p = it->second;
+        got = it->first;
+        ctx->pool_bytes -= got;
+        ctx->pool.erase(it);
+    } else {
+        hipError_t e = hipMalloc(&p, bytes);
+        if (e != hipSuccess && !ctx->pool.empty()) {
+            (void)hipGetLastError();
+            pool_trim(ctx, 0);
+            e = hipMalloc(&p, bytes);
+        }
+        if (e != hipSuccess) return fail(PT_ENOMEM, "hipMalloc(" + std::to_string(bytes) + "): " + hipGetErrorString(e));
+    }
+    pl->allocs.push_back({p, got});
+    pl->device_bytes += (int64_t)got;
     *out = reinterpret_cast<P *>(p);
     return PT_OK;
 }
 
+// Destroys a plan; its device blocks go to the context's pool once the
+// device has finished any work that may still use them.
 void free_plan(pt_plan *pl) {
     if (!pl) return;
     for (auto &kv : pl->execs) (void)hipGraphExecDestroy(kv.second);
-    for (void *p : pl->allocs) (void)hipFree(p);
+    if (!pl->allocs.empty()) {
+        pt_ctx *ctx = pl->ctx;
+        (void)hipSetDevice(ctx->device);
+        (void)hipDeviceSynchronize();
+        for (const auto &a : pl->allocs) {
+            ctx->pool.emplace(a.second, a.first);
+            ctx->pool_bytes += a.second;
+        }
+        pool_trim(ctx, pool_cap());
+    }
     delete pl;
 }
 
@@ -249,11 +306,9 @@ pt_status configure_shape(pt_plan *pl, int block, int groups = 1) {
     if (!lds_ok) {
         size_t need = (size_t)grid * tab_lds;
         if (need > pl->tab_bytes) {
-            void *p = nullptr;
-            hipError_t e = hipMalloc(&p, need);
-            if (e != hipSuccess) return fail(PT_ENOMEM, std::string("hipMalloc(eigenbasis tables): ") + hipGetErrorString(e));
-            pl->allocs.push_back(p);
-            pl->device_bytes += (int64_t)need;
+            char *p = nullptr;
+            pt_status st = dev_alloc(pl, &p, need);
+            if (st) return st;
             pl->d_tab = p;
             pl->tab_bytes = need;
         }
@@ -739,6 +794,8 @@ pt_status pt_ctx_create(int32_t device, pt_ctx **out) {
 void pt_ctx_destroy(pt_ctx *ctx) {
     if (!ctx) return;
     (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    pool_trim(ctx, 0);
     if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
 }

@@ -291,3 +291,28 @@ def test_abi_errors(ctx):
     assert ps[0] == 1 and st[0] == 1
     # empty batch
     assert len(pt.pt_batch_loglik(ctx, [A], pt.Trees([]), np.zeros(0))) == 0
+
+
+@pytest.mark.parametrize("pool_cap", [None, "0"])
+def test_plan_memory_reuse(monkeypatch, pool_cap):
+    """Destroyed plans leave their device blocks with the context for later
+    plans; results must not depend on whether a plan's memory is fresh or
+    reused (PT_POOL_CAP_BYTES=0 turns the keeping off)."""
+    if pool_cap is not None:
+        monkeypatch.setenv("PT_POOL_CAP_BYTES", pool_cap)
+    c = pt.Context(0)
+    rng = np.random.default_rng(61)
+    e, b = synth.yule_tree(16, rng, mean=0.08)
+    aln = synth.make_alignment(e, b, 16, 700, rng, alpha=0.5, n_cats=4)
+    A = pt.Alignment.from_synth(c, aln)
+    ne, nb, _ = pt.pt_nni_neighbors(16, e, b)
+    runs = []
+    for trees in (ne, ne, ne[:5]):  # the same plan twice, then a smaller one in the larger blocks
+        l, bo, ps, st = pt.pt_batch_optimize_branches(c, [A], pt.Trees(list(trees)), nb[:len(trees)].ravel(),
+                                                      precision=pt.PT_FP32)
+        runs.append((l, bo))
+    assert np.array_equal(runs[0][0], runs[1][0]) and np.array_equal(runs[0][1], runs[1][1])
+    assert np.array_equal(runs[2][0], runs[0][0][:5])
+    D = oc.Data.from_alignment(aln)
+    assert abs(runs[2][0][0] - oc.optimize(D, ne[0], nb[0])[0]) < FP32_ABS
+    c.close()
