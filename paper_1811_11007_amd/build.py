@@ -25,7 +25,7 @@ def build(verbose: bool = False) -> str:
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = ["hipcc", "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-shared",
            "-Wall", "-Wno-unused-function", "-I", os.path.join(ROOT, "include"),
-           "-I", os.path.join(HERE, "csrc")] + HIP_FLAGS + sources() + ["-o", tmp]
+           "-I", os.path.join(HERE, "csrc")] + HIP_FLAGS + sources() + ["-pthread", "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)

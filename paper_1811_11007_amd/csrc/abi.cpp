@@ -16,6 +16,7 @@
 #include <memory>
 #include <numeric>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "kernels.hpp"
@@ -358,75 +359,105 @@ pt_status plan_build(pt_ctx *ctx, pt_aln *const *alns, int32_t n_alns, const pt_
     const int64_t tile_pats = (int64_t)pt::kTileBlock * pt::kTileItems;
     const int kp = kp_of_plan(alns, trees);
     pl->kp = kp;
-    std::string err;
-    for (int b = 0; b < B; ++b) {
-        const pt_aln *al = alns[trees->aln_index[b]];
-        const AlnDev &ad = al->desc;
+    // Trees compile independently, on up to 16 host threads (a search
+    // builds a plan of about a thousand trees for every batch); offsets and
+    // the concatenated program follow in tree order.
+    struct Compiled {
+        pt_status st = PT_OK;
+        std::string err;
+        int E = 0, n_slots = 0;
+        bool any = true;
+        std::vector<Op> ll, gr, p1, p2, p3;
+    };
+    std::vector<Compiled> cp(B);
+    auto compile_tree = [&](int b) {
+        Compiled &c = cp[b];
+        const AlnDev &ad = alns[trees->aln_index[b]]->desc;
         pt::Tree t;
         const int32_t *ed = trees->edges + 2 * trees->edge_offset[b];
-        st = pt::build_tree(ntx[b], ed, t, err);
-        if (st) return fail(st, "tree " + std::to_string(b) + ": " + err);
-        const int E = t.n_edges;
-        if ((size_t)E * kp * 16 * 8 + (size_t)E * 8 > kLdsBudget)
-            return fail(PT_EUNSUPPORTED, "tree " + std::to_string(b) + ": (2n-3) * padded categories exceeds the 64 KiB "
-                                         "transition-matrix cache (at most 504 edge-categories)");
-        if ((kinds & PT_PLAN_OPTIMIZE) && ad.P > kMaxOptPatterns)
-            return fail(PT_EUNSUPPORTED, "tree " + std::to_string(b) + ": more than 32768 patterns "
-                                         "for branch optimisation");
+        std::string err;
+        c.st = pt::build_tree(ntx[b], ed, t, err);
+        if (c.st) { c.err = "tree " + std::to_string(b) + ": " + err; return; }
+        c.E = t.n_edges;
+        c.n_slots = t.n_slots();
+        if ((size_t)c.E * kp * 16 * 8 + (size_t)c.E * 8 > kLdsBudget) {
+            c.st = PT_EUNSUPPORTED;
+            c.err = "tree " + std::to_string(b) + ": (2n-3) * padded categories exceeds the 64 KiB "
+                    "transition-matrix cache (at most 504 edge-categories)";
+            return;
+        }
+        if ((kinds & PT_PLAN_OPTIMIZE) && ad.P > kMaxOptPatterns) {
+            c.st = PT_EUNSUPPORTED;
+            c.err = "tree " + std::to_string(b) + ": more than 32768 patterns for branch optimisation";
+            return;
+        }
+        if (kinds & PT_PLAN_LOGLIK) pt::compile_loglik(t, c.ll);
+        if (kinds & PT_PLAN_GRAD) pt::compile_grad(t, c.gr);
+        if (kinds & PT_PLAN_OPTIMIZE) {
+            const uint8_t *m = mask ? mask + trees->edge_offset[b] : nullptr;
+            c.any = !m;
+            for (int e = 0; m && e < c.E; ++e) c.any |= m[e] != 0;
+            if (c.any) pt::compile_optimize(t, m, c.p1, c.p2);
+            else pt::compile_loglik(t, c.p1);
+            if (precision == PT_FP32) pt::compile_loglik_dense(t, c.p3);
+        }
+    };
+    {
+        const int hw = (int)std::max(1u, std::thread::hardware_concurrency());
+        const int nt = std::max(1, std::min({hw, 16, (B + 31) / 32}));
+        if (nt == 1) {
+            for (int b = 0; b < B; ++b) compile_tree(b);
+        } else {
+            std::vector<std::thread> pool;
+            for (int w = 0; w < nt; ++w)
+                pool.emplace_back([&, w]() {
+                    for (int b = w; b < B; b += nt) compile_tree(b);
+                });
+            for (auto &th : pool) th.join();
+        }
+    }
+    for (int b = 0; b < B; ++b)
+        if (cp[b].st) return fail(cp[b].st, cp[b].err);
+    for (int b = 0; b < B; ++b) {
+        Compiled &c = cp[b];
+        const AlnDev &ad = alns[trees->aln_index[b]]->desc;
+        const int E = c.E;
         pl->max_P = std::max(pl->max_P, ad.P);
         pl->max_E = std::max(pl->max_E, E);
         pl->tree_E.push_back(E);
         TreeDev base{};
         base.aln = b;  // every tree has a descriptor of its own (per-tree Gamma shape)
         base.n_edges = E;
-        base.n_slots = t.n_slots();
+        base.n_slots = c.n_slots;
         base.clv_off = clv_off;
         base.cnt_off = cnt_off;
         base.edge_off = trees->edge_offset[b];
         base.pm_off = pm_off;
         base.n_tiles = (int)((ad.P + tile_pats - 1) / tile_pats);
         base.tile_begin = 0;  // assigned below, longest programs first
-        clv_off += (int64_t)t.n_slots() * kp * ad.P * 4;
-        cnt_off += (int64_t)t.n_slots() * ad.P;
+        clv_off += (int64_t)c.n_slots * kp * ad.P * 4;
+        cnt_off += (int64_t)c.n_slots * ad.P;
         pm_off += (int64_t)E * kp * 16;
         for (int64_t i = 0; i < E; ++i) edge_tree[base.edge_off + i] = b;
         tll[b] = tgr[b] = top[b] = base;
-        if (kinds & PT_PLAN_LOGLIK) {
-            std::vector<Op> p;
-            pt::compile_loglik(t, p);
-            tll[b].op_first = (int32_t)ops.size();
-            tll[b].n_first = (int32_t)p.size();
-            ops.insert(ops.end(), p.begin(), p.end());
-        }
-        if (kinds & PT_PLAN_GRAD) {
-            std::vector<Op> p;
-            pt::compile_grad(t, p);
-            tgr[b].op_first = (int32_t)ops.size();
-            tgr[b].n_first = (int32_t)p.size();
-            ops.insert(ops.end(), p.begin(), p.end());
-        }
+        auto append = [&](const std::vector<Op> &v, int32_t &first, int32_t &count) {
+            first = (int32_t)ops.size();
+            count = (int32_t)v.size();
+            ops.insert(ops.end(), v.begin(), v.end());
+        };
+        if (kinds & PT_PLAN_LOGLIK) append(c.ll, tll[b].op_first, tll[b].n_first);
+        if (kinds & PT_PLAN_GRAD) append(c.gr, tgr[b].op_first, tgr[b].n_first);
         if (kinds & PT_PLAN_OPTIMIZE) {
-            const uint8_t *m = mask ? mask + base.edge_off : nullptr;
-            bool any = !m;
-            for (int e = 0; m && e < E; ++e) any |= m[e] != 0;
-            std::vector<Op> p1, p2;
-            if (any) pt::compile_optimize(t, m, p1, p2);
-            else pt::compile_loglik(t, p1);
-            top[b].op_first = (int32_t)ops.size();
-            top[b].n_first = (int32_t)p1.size();
-            ops.insert(ops.end(), p1.begin(), p1.end());
-            top[b].op_steady = (int32_t)ops.size();
-            top[b].n_steady = (int32_t)p2.size();
-            ops.insert(ops.end(), p2.begin(), p2.end());
-            if (precision == PT_FP32) {
-                std::vector<Op> p3;
-                pt::compile_loglik_dense(t, p3);
-                top[b].op_final = (int32_t)ops.size();
-                top[b].n_final = (int32_t)p3.size();
-                ops.insert(ops.end(), p3.begin(), p3.end());
-            }
-            cost[b] = (double)ad.P * ad.K * (double)(p2.size() + 1);
+            append(c.p1, top[b].op_first, top[b].n_first);
+            append(c.p2, top[b].op_steady, top[b].n_steady);
+            if (precision == PT_FP32) append(c.p3, top[b].op_final, top[b].n_final);
+            cost[b] = (double)ad.P * ad.K * (double)(c.p2.size() + 1);
         }
+        std::vector<Op>().swap(c.ll);
+        std::vector<Op>().swap(c.gr);
+        std::vector<Op>().swap(c.p1);
+        std::vector<Op>().swap(c.p2);
+        std::vector<Op>().swap(c.p3);
     }
     if (kinds & (PT_PLAN_LOGLIK | PT_PLAN_GRAD)) {
         // Tiles of the trees with the longest programs first: the hardware
