@@ -102,8 +102,8 @@ def main():
                          "calibrates hardware byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build runs the batch on a single MI355X "
-              "(topologies shard across GPUs with no collective; see DESIGN.md). Use --gpus 1.",
+        print("bench.py measures one GPU: the batch runs on a single MI355X "
+              "(topologies shard across GPUs with no collective). Use --gpus 1.",
               file=sys.stderr)
         sys.exit(2)
 

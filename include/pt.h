@@ -43,7 +43,7 @@ typedef int32_t pt_status;
 #define PT_EINVAL (-1)        /* an argument failed validation */
 #define PT_ENOMEM (-2)        /* host or device allocation failed, or the arena cap */
 #define PT_EDEVICE (-3)       /* a HIP runtime call failed */
-#define PT_EUNSUPPORTED (-4)  /* valid input beyond this build's limits */
+#define PT_EUNSUPPORTED (-4)  /* valid input beyond the library's limits */
 #define PT_EINTERNAL (-5)
 
 #define PT_FP64 0
@@ -61,7 +61,9 @@ const char *pt_last_error(void);
  * Device memory of destroyed plans stays with the context for later plans
  * (a new plan takes a kept block of one to two times the size it needs), up
  * to PT_POOL_CAP_BYTES (decimal, default 64 GiB); a failing allocation first
- * returns the kept blocks to the device.  pt_ctx_destroy frees them. */
+ * returns the kept blocks to the device.  pt_ctx_destroy frees them; a plan
+ * that outlives its context may still be destroyed (its memory is then freed
+ * when the last such plan goes), but no other call may use it. */
 typedef struct pt_ctx pt_ctx;
 pt_status pt_ctx_create(int32_t device, pt_ctx **out);
 void pt_ctx_destroy(pt_ctx *ctx);
@@ -180,7 +182,8 @@ pt_status pt_plan_create(pt_ctx *ctx, pt_aln *const *alns, int32_t n_alns,
                          const pt_trees *trees, const uint8_t *opt_mask,
                          int32_t precision, int32_t kinds, pt_plan **out);
 /* Waits for the device to finish, then gives the plan's device memory back
- * to its context (see pt_ctx_create). */
+ * to its context's kept blocks (see pt_ctx_create); valid also after the
+ * context was destroyed. */
 void pt_plan_destroy(pt_plan *plan);
 pt_status pt_plan_set_graphs(pt_plan *plan, int32_t enable);
 

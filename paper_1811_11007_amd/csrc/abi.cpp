@@ -58,6 +58,20 @@ int64_t arena_cap() {
 
 }  // namespace
 
+// Device blocks of destroyed plans, kept for later plans (size -> block).
+// Shared by a context and its plans, so a plan destroyed after its context
+// still has somewhere to return its memory; the last owner frees the blocks.
+struct DevicePool {
+    int device = 0;
+    std::multimap<size_t, void *> blocks;
+    size_t bytes = 0;
+    ~DevicePool() {
+        if (blocks.empty()) return;
+        (void)hipSetDevice(device);
+        for (auto &b : blocks) (void)hipFree(b.second);
+    }
+};
+
 struct pt_ctx {
     int device = 0;
     int n_cu = 0;
@@ -66,12 +80,10 @@ struct pt_ctx {
     // tuned (threads per block, blocks per tree) of the optimisation kernel,
     // per (precision, padded categories, largest pattern count)
     std::map<std::tuple<int, int, int>, std::pair<int, int>> tuned;
-    // device blocks of destroyed plans, kept for later plans (size -> block):
-    // a search creates a plan of the same size for every batch, and a fresh
-    // hipMalloc / hipFree of tens of GB each time cost far more than the
-    // optimisation itself
-    std::multimap<size_t, void *> pool;
-    size_t pool_bytes = 0;
+    // device memory of destroyed plans: a search creates a plan of the same
+    // size for every batch, and a fresh hipMalloc / hipFree of tens of GB
+    // each time cost far more than the optimisation itself
+    std::shared_ptr<DevicePool> pool = std::make_shared<DevicePool>();
 };
 
 struct pt_aln {
@@ -108,6 +120,7 @@ struct pt_plan {
     bool graphs = false;
     std::map<std::vector<uint64_t>, hipGraphExec_t> execs;
     std::vector<std::pair<void *, size_t>> allocs;  // device blocks and their sizes
+    std::shared_ptr<DevicePool> pool;                // where they go when the plan is destroyed
     // host copies for traffic accounting
     std::vector<Op> ops_h;
     std::vector<TreeDev> tll_h, tgr_h, top_h;
@@ -130,12 +143,12 @@ size_t pool_cap() {
     return (size_t)64 << 30;
 }
 
-void pool_trim(pt_ctx *ctx, size_t cap) {
-    while (ctx->pool_bytes > cap && !ctx->pool.empty()) {
-        auto it = std::prev(ctx->pool.end());
+void pool_trim(DevicePool *pool, size_t cap) {
+    while (pool->bytes > cap && !pool->blocks.empty()) {
+        auto it = std::prev(pool->blocks.end());
         (void)hipFree(it->second);
-        ctx->pool_bytes -= it->first;
-        ctx->pool.erase(it);
+        pool->bytes -= it->first;
+        pool->blocks.erase(it);
     }
 }
 
@@ -144,22 +157,22 @@ void pool_trim(pt_ctx *ctx, size_t cap) {
 // initialise everything they read, so a reused block needs no clearing.
 template <typename P>
 pt_status dev_alloc(pt_plan *pl, P **out, size_t bytes) {
-    pt_ctx *ctx = pl->ctx;
+    DevicePool *pool = pl->pool.get();
     bytes = std::max<size_t>(bytes, 16);
     bytes = (bytes + 255) & ~(size_t)255;
     void *p = nullptr;
     size_t got = bytes;
-    auto it = ctx->pool.lower_bound(bytes);
-    if (it != ctx->pool.end() && it->first <= 2 * bytes) {
+    auto it = pool->blocks.lower_bound(bytes);
+    if (it != pool->blocks.end() && it->first <= 2 * bytes) {
         p = it->second;
         got = it->first;
-        ctx->pool_bytes -= got;
-        ctx->pool.erase(it);
+        pool->bytes -= got;
+        pool->blocks.erase(it);
     } else {
         hipError_t e = hipMalloc(&p, bytes);
-        if (e != hipSuccess && !ctx->pool.empty()) {
+        if (e != hipSuccess && !pool->blocks.empty()) {
             (void)hipGetLastError();
-            pool_trim(ctx, 0);
+            pool_trim(pool, 0);
             e = hipMalloc(&p, bytes);
         }
         if (e != hipSuccess) return fail(PT_ENOMEM, "hipMalloc(" + std::to_string(bytes) + "): " + hipGetErrorString(e));
@@ -170,20 +183,21 @@ pt_status dev_alloc(pt_plan *pl, P **out, size_t bytes) {
     return PT_OK;
 }
 
-// Destroys a plan; its device blocks go to the context's pool once the
-// device has finished any work that may still use them.
+// Destroys a plan; its device blocks go to the pool once the device has
+// finished any work that may still use them (the pool outlives the plan's
+// context if need be).
 void free_plan(pt_plan *pl) {
     if (!pl) return;
     for (auto &kv : pl->execs) (void)hipGraphExecDestroy(kv.second);
     if (!pl->allocs.empty()) {
-        pt_ctx *ctx = pl->ctx;
-        (void)hipSetDevice(ctx->device);
+        DevicePool *pool = pl->pool.get();
+        (void)hipSetDevice(pool->device);
         (void)hipDeviceSynchronize();
         for (const auto &a : pl->allocs) {
-            ctx->pool.emplace(a.second, a.first);
-            ctx->pool_bytes += a.second;
+            pool->blocks.emplace(a.second, a.first);
+            pool->bytes += a.second;
         }
-        pool_trim(ctx, pool_cap());
+        pool_trim(pool, pool_cap());
     }
     delete pl;
 }
@@ -345,6 +359,7 @@ pt_status plan_build(pt_ctx *ctx, pt_aln *const *alns, int32_t n_alns, const pt_
 
     std::unique_ptr<pt_plan, void (*)(pt_plan *)> pl(new pt_plan, free_plan);
     pl->ctx = ctx;
+    pl->pool = ctx->pool;
     pl->precision = precision;
     pl->kinds = kinds;
     pl->n_trees = B;
@@ -810,6 +825,7 @@ pt_status pt_ctx_create(int32_t device, pt_ctx **out) {
     if (device < 0 || device >= n) return fail(PT_EINVAL, "device index out of range");
     auto *c = new pt_ctx;
     c->device = device;
+    c->pool->device = device;
     hipDeviceProp_t prop;
     if ((e = hipSetDevice(device)) != hipSuccess || (e = hipGetDeviceProperties(&prop, device)) != hipSuccess ||
         (e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking)) != hipSuccess) {
@@ -826,7 +842,7 @@ void pt_ctx_destroy(pt_ctx *ctx) {
     if (!ctx) return;
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
-    pool_trim(ctx, 0);
+    pool_trim(ctx->pool.get(), 0);  // plans still alive keep the pool itself
     if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
 }

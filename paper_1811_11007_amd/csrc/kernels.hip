@@ -16,8 +16,14 @@
 // exact, so it changes no value.
 //
 // Sums over patterns are fixed-order: butterfly within a wavefront, then the
-// per-wave partials in wave order, then the tiles of a tree in tile order, so
-// a rerun is bit-identical.
+// per-wave partials in wave order, then the tiles of a tree in tile order (or,
+// for a tree optimised by several blocks, the blocks in block order), so a
+// rerun is bit-identical.
+//
+// Kernels: k_pmat (transition matrices), k_tiles32 / k_tiles64 (a tree's
+// likelihood or gradient program over one pattern tile), k_reduce (tile sums
+// in order), k_optimize (the whole branch-length smoothing loop of a tree,
+// one block per tree or one tree split over several blocks).
 #include <hip/hip_runtime.h>
 
 #include <cmath>

@@ -316,3 +316,36 @@ def test_plan_memory_reuse(monkeypatch, pool_cap):
     D = oc.Data.from_alignment(aln)
     assert abs(runs[2][0][0] - oc.optimize(D, ne[0], nb[0])[0]) < FP32_ABS
     c.close()
+
+
+@pytest.mark.gpu
+def test_plan_destroyed_after_context():
+    """A plan destroyed after its context returns its memory to kept blocks
+    that outlive the context; a new context's plans are unaffected."""
+    import torch
+    c = pt.Context(0)
+    rng = np.random.default_rng(62)
+    e, b = synth.yule_tree(12, rng, mean=0.08)
+    aln = synth.make_alignment(e, b, 12, 400, rng)
+    A = pt.Alignment.from_synth(c, aln)
+    ne, nb, _ = pt.pt_nni_neighbors(12, e, b)
+    plans = [pt.Plan(c, [A], pt.Trees(list(ne)), pt.PT_PLAN_LOGLIK, precision=pt.PT_FP64) for _ in range(2)]
+    d_b = torch.tensor(nb.ravel(), dtype=torch.float64, device="cuda")
+    d_l = torch.zeros(len(ne), dtype=torch.float64, device="cuda")
+    plans[0].loglik(d_b, d_l)
+    torch.cuda.synchronize()
+    first = d_l.cpu().numpy().copy()
+    plans[0].close()  # into the context's kept blocks
+    A.close()
+    c.close()
+    plans[1].close()  # the context is gone: its memory is freed with the last plan
+    c2 = pt.Context(0)
+    A2 = pt.Alignment.from_synth(c2, aln)
+    p2 = pt.Plan(c2, [A2], pt.Trees(list(ne)), pt.PT_PLAN_LOGLIK, precision=pt.PT_FP64)
+    d_l.zero_()
+    p2.loglik(d_b, d_l)
+    torch.cuda.synchronize()
+    assert np.array_equal(d_l.cpu().numpy(), first)
+    D = oc.Data.from_alignment(aln)
+    assert abs(first[0] - oc.loglik(D, ne[0], nb[0])) <= 1e-6 * abs(first[0])
+    p2.close(); A2.close(); c2.close()

@@ -168,7 +168,7 @@ def test_warm_start_gain_on_held_out_alignment(ctx):
         search) started from the better of the two starts reach partial
         likelihoods closer to the full optima.
     The full optima are the same from either start: the network moves only
-    the starting point (the cold-start optimum is the judge)."""
+    the starting point (the cold-start optimum is the reference)."""
     import torch
     from paper_1811_11007_amd.search import WarmStart
     from paper_1811_11007_amd.train_warmstart import optimise_start, workload
