@@ -50,10 +50,11 @@ struct Store<float> {
         x[0] = v.x; x[1] = v.y; x[2] = v.z; x[3] = v.w;
     }
     __device__ static inline double as_stored(double x) { return (double)(float)x; }
-    __device__ static inline void store(float *p, const double x[4]) {
-        *reinterpret_cast<float4 *>(p) =
-            make_float4((float)x[0], (float)x[1], (float)x[2], (float)x[3]);
+    __device__ static inline Raw pack(const double x[4]) {
+        return make_float4((float)x[0], (float)x[1], (float)x[2], (float)x[3]);
     }
+    __device__ static inline void store_raw(float *p, const Raw &r) { *reinterpret_cast<float4 *>(p) = r; }
+    __device__ static inline void store(float *p, const double x[4]) { store_raw(p, pack(x)); }
 };
 
 template <>
@@ -72,6 +73,16 @@ struct Store<double> {
         x[0] = v.a.x; x[1] = v.a.y; x[2] = v.b.x; x[3] = v.b.y;
     }
     __device__ static inline double as_stored(double x) { return x; }
+    __device__ static inline Raw pack(const double x[4]) {
+        Raw r;
+        r.a = make_double2(x[0], x[1]);
+        r.b = make_double2(x[2], x[3]);
+        return r;
+    }
+    __device__ static inline void store_raw(double *p, const Raw &r) {
+        reinterpret_cast<double2 *>(p)[0] = r.a;
+        reinterpret_cast<double2 *>(p)[1] = r.b;
+    }
     __device__ static inline void store(double *p, const double x[4]) {
         reinterpret_cast<double2 *>(p)[0] = make_double2(x[0], x[1]);
         reinterpret_cast<double2 *>(p)[1] = make_double2(x[2], x[3]);
@@ -346,6 +357,48 @@ __device__ inline typename PmPtr<PM>::type pm_base(const V &v) {
     else return (typename PmPtr<PM>::type)v.pm;
 }
 
+// One pattern of an OP_UPDATE from its two fetched sides, for the fused
+// update and table build: o[k] and the returned scaler count are what
+// update_sides computes, by the same expressions in the same order (so both
+// paths give identical partials; update_sides keeps its own copy because
+// sharing this one changed the register allocation of the FP32 kernels and
+// slowed them).
+template <typename T, int KP, int PM, class SA, class SB>
+__device__ inline int update_pattern(const TreeView<T> &v, const Op &op, const SA &sa, const SB &sb,
+                                     double o[KP][4]) {
+    const auto pm = pm_base<PM>(v);
+    const double thr = ldexp(1.0, -Store<T>::kScaleExp);
+    const double up = ldexp(1.0, Store<T>::kScaleExp);
+    double mx = 0.0;
+#pragma unroll
+    for (int k = 0; k < KP; ++k) {
+        double xa[4], xb[4];
+        sa.get(k, xa);
+        sb.get(k, xb);
+        const auto Pa = pm + ((size_t)op.ea * KP + k) * 16;
+        const auto Pb = pm + ((size_t)op.eb * KP + k) * 16;
+        const bool live = k < v.K;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const double xsa = Pa[i * 4] * xa[0] + Pa[i * 4 + 1] * xa[1] + Pa[i * 4 + 2] * xa[2] +
+                               Pa[i * 4 + 3] * xa[3];
+            const double xsb = Pb[i * 4] * xb[0] + Pb[i * 4 + 1] * xb[1] + Pb[i * 4 + 2] * xb[2] +
+                               Pb[i * 4 + 3] * xb[3];
+            o[k][i] = live ? xsa * xsb : 0.0;
+            mx = fmax(mx, o[k][i]);
+        }
+    }
+    int c = sa.c + sb.c;
+    if (mx < thr && mx > 0.0) {
+#pragma unroll
+        for (int k = 0; k < KP; ++k)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) o[k][i] *= up;
+        c += 1;
+    }
+    return c;
+}
+
 // OP_UPDATE for this thread's patterns, sides of kinds TA / TB (tip or slot):
 //   dst[k] = (P_k(t_ea) . side a[k]) * (P_k(t_eb) . side b[k]), elementwise over
 // states, for every category k, then per-pattern scaling.
@@ -502,6 +555,49 @@ struct EdgeResult {
     long long cyc_table, cyc_iters;
 };
 
+// One row of an edge's eigenbasis table from the pattern's two sides (the
+// table is symmetric in them), for the fused update and table build: the
+// row, weight and sums that table_sides gives for the pattern, by the same
+// expressions in the same order (table_sides keeps its own copy for the same
+// reason as update_sides).  Stores the row of every live category into tab
+// ([k][row][4]) and the weight into wrow, adds the pattern's t-independent
+// lnL term to cterm and, with FUSE, its terms of the first Newton iteration
+// at the exponentials wxe to f1 and f2.
+template <typename T, int KP, bool FUSE, class SA, class SB, typename X>
+__device__ inline void table_row(const TreeView<T> &v, const SA &sa, const SB &sb, int p, size_t rows, T *tab,
+                                 double *wrow, double w, double logK, const X *wxe, double &cterm, double &f1,
+                                 double &f2) {
+    const ModelS *md = v.m;
+    cterm += w * const_term<T>(sa.c + sb.c, logK);
+    wrow[p] = w;
+    double L = 0.0, L1 = 0.0, L2 = 0.0;
+#pragma unroll
+    for (int k = 0; k < KP; ++k) {
+        if (k < v.K) {
+            double xa[4], xb[4], sk[4];
+            sa.get(k, xa);
+            sb.get(k, xb);
+            coeffs_x(md, xa, xb, sk);
+            Store<T>::store(tab + ((size_t)k * rows + p) * 4, sk);
+            if constexpr (FUSE) {
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    const double q = Store<T>::as_stored(sk[m]);
+                    L += q * (double)wxe[k * 4 + m];
+                    L1 += q * (double)wxe[4 * kMaxCats + k * 4 + m];
+                    L2 += q * (double)wxe[8 * kMaxCats + k * 4 + m];
+                }
+            }
+        }
+    }
+    if constexpr (FUSE) {
+        const double ia = recip(L);
+        const double r1 = L1 * ia;
+        f1 += w * r1;
+        f2 += w * (L2 * ia - r1 * r1);
+    }
+}
+
 // The eigenbasis table of an edge whose sides are of kinds TA / TB: this
 // thread's rows of tab ([k][row][4]) and wrow; returns the sum of its rows'
 // t-independent lnL terms.  FUSE: also adds the rows' terms of the first
@@ -592,6 +688,42 @@ __device__ inline double table_sides(const TreeView<T> &v, int a, int b, int ni,
     return cterm;
 }
 
+// An OP_UPDATE whose output is one side of the next OP_NEWTON, with one
+// pattern per thread: the update's loads and those of the edge's other side
+// (kind TO) issue together, and the edge's table row is built from the
+// update's output, kept in registers and rounded as stored, instead of being
+// read back.  The table is symmetric in the two sides, so which side the
+// update made does not matter.  Returns the row's t-independent lnL term
+// (see table_row).
+template <typename T, int BS, int KP, bool TA, bool TB, bool TO, bool FUSE, int PM, typename X>
+__device__ inline double update_table_sides(const TreeView<T> &v, const Op &op, int other, T *tab, double *wrow,
+                                            double logK, const X *wxe, double &f1, double &f2) {
+    double cterm = 0.0;
+    const int p = threadIdx.x;
+    if (p < v.np) {
+        Side<T, KP, TA> sa;
+        Side<T, KP, TB> sb;
+        Side<T, KP, TO> so;
+        sa.fetch(v, op.a, p);
+        sb.fetch(v, op.b, p);
+        so.fetch(v, other, p);
+        const double w = ldg(v.w + p);
+        Side<T, KP, false> made;
+        {
+            double o[KP][4];
+            made.c = update_pattern<T, KP, PM>(v, op, sa, sb, o);
+#pragma unroll
+            for (int k = 0; k < KP; ++k) made.r[k] = Store<T>::pack(o[k]);
+        }
+        table_row<T, KP, FUSE>(v, made, so, p, (size_t)BS, tab, wrow, w, logK, wxe, cterm, f1, f2);
+#pragma unroll
+        for (int k = 0; k < KP; ++k)
+            if (k < v.K) Store<T>::store_raw(slot_ptr<T, KP>(v, op.dst, k, p), made.r[k]);
+        v.cnt[(size_t)op.dst * v.P + p] = (uint16_t)made.c;
+    }
+    return cterm;
+}
+
 // Newton pass over two table rows r0 and r1 (r1 < 0: only r0), so that each
 // exponential read from the wave's LDS slice serves two patterns.  Adds the
 // rows' d1 and d2 terms, or with lnl_only their weighted log L to d0; each
@@ -675,32 +807,89 @@ constexpr double kNewtonAccept = 0.03;
 //  - with want_lnl, lnL is evaluated at the returned t.
 // All threads hold identical block totals, so every thread takes the same
 // decisions.
-template <typename T, int BS, int KP>
-__device__ inline EdgeResult newton_edge(const TreeView<T> &v, int a, int b, double t, bool want_lnl,
-                                         const OptParams &opt, T *tab, double *wrow, int ni, double *red,
-                                         double *wx, float *wxf, int parity, GroupS *gs) {
-    const ModelS *md = v.m;
-    const size_t rows = (size_t)BS * ni;
-    const double logK = log((double)v.K);
-    const long long c0 = clock64();
-    // the first iteration's derivative terms are summed while the table is
-    // built (with the same rounding and order as the row passes below)
+// An edge's table built ahead of newton_edge (by update_table_sides): this
+// thread's t-independent lnL term and first-iteration derivative terms.
+struct EdgePre {
+    double cterm, f1, f2;
+};
+
+// The first iteration's derivative terms are summed while the table is built
+// (with the same rounding and order as the row passes of newton_edge), up to
+// four padded categories: with eight the extra registers would spill.
+template <int KP>
+struct FuseFirst {
+    static constexpr bool value = KP <= 4;
+};
+
+// The exponentials of length t that the fused first iteration uses (in the
+// wave's LDS slice), and a pointer to them in the precision it reads.
+template <typename T, int KP>
+__device__ inline const typename std::conditional<std::is_same<T, float>::value, float, double>::type *
+first_expo(const TreeView<T> &v, double t, double *wx, float *wxf) {
     constexpr bool kF = std::is_same<T, float>::value;
-    constexpr bool kFuse = KP <= 4;  // with eight categories the extra registers would spill
     using XE = typename std::conditional<kF, float, double>::type;
-    if constexpr (kFuse) {
+    if constexpr (FuseFirst<KP>::value) {
         if constexpr (kF) wave_expo(wx, v.m, v.K, t, wxf);
         else wave_expo(wx, v.m, v.K, t);
     }
-    const XE *wxe = kF ? reinterpret_cast<const XE *>(wxf) : reinterpret_cast<const XE *>(wx);
+    return kF ? reinterpret_cast<const XE *>(wxf) : reinterpret_cast<const XE *>(wx);
+}
+
+// OP_UPDATE of slot op.dst fused with the table build of the next OP_NEWTON,
+// whose other side is `other`, at its current length t (one pattern per
+// thread).
+template <typename T, int BS, int KP, int PM>
+__device__ inline EdgePre update_and_table(const TreeView<T> &v, const Op &op, int other, double t, T *tab,
+                                           double *wrow, double *wx, float *wxf) {
+    constexpr bool kFuse = FuseFirst<KP>::value;
+    const auto *wxe = first_expo<T, KP>(v, t, wx, wxf);
+    const double logK = log((double)v.K);
+    EdgePre pre;
+    pre.f1 = pre.f2 = 0.0;
+#define PT_UT(TA, TB, TO)                                                                                        \
+    pre.cterm = update_table_sides<T, BS, KP, TA, TB, TO, kFuse, PM>(v, op, other, tab, wrow, logK, wxe, pre.f1, \
+                                                                      pre.f2)
+    if (op.a < 0) {
+        if (op.b < 0) {
+            if (other < 0) PT_UT(true, true, true); else PT_UT(true, true, false);
+        } else {
+            if (other < 0) PT_UT(true, false, true); else PT_UT(true, false, false);
+        }
+    } else {
+        if (op.b < 0) {
+            if (other < 0) PT_UT(false, true, true); else PT_UT(false, true, false);
+        } else {
+            if (other < 0) PT_UT(false, false, true); else PT_UT(false, false, false);
+        }
+    }
+#undef PT_UT
+    return pre;
+}
+
+template <typename T, int BS, int KP>
+__device__ inline EdgeResult newton_edge(const TreeView<T> &v, int a, int b, double t, bool want_lnl,
+                                         const OptParams &opt, T *tab, double *wrow, int ni, double *red,
+                                         double *wx, float *wxf, int parity, GroupS *gs,
+                                         const EdgePre *pre = nullptr) {
+    const size_t rows = (size_t)BS * ni;
+    const double logK = log((double)v.K);
+    const long long c0 = clock64();
+    constexpr bool kFuse = FuseFirst<KP>::value;
     double f1 = 0.0, f2 = 0.0;
     double cterm;
-    if (a < 0) {
-        if (b < 0) cterm = table_sides<T, BS, KP, true, true, kFuse>(v, a, b, ni, rows, tab, wrow, logK, wxe, f1, f2);
-        else cterm = table_sides<T, BS, KP, true, false, kFuse>(v, a, b, ni, rows, tab, wrow, logK, wxe, f1, f2);
+    if (pre) {  // the table is built (one pattern per thread)
+        cterm = pre->cterm;
+        f1 = pre->f1;
+        f2 = pre->f2;
     } else {
-        if (b < 0) cterm = table_sides<T, BS, KP, false, true, kFuse>(v, a, b, ni, rows, tab, wrow, logK, wxe, f1, f2);
-        else cterm = table_sides<T, BS, KP, false, false, kFuse>(v, a, b, ni, rows, tab, wrow, logK, wxe, f1, f2);
+        const auto *wxe = first_expo<T, KP>(v, t, wx, wxf);
+        if (a < 0) {
+            if (b < 0) cterm = table_sides<T, BS, KP, true, true, kFuse>(v, a, b, ni, rows, tab, wrow, logK, wxe, f1, f2);
+            else cterm = table_sides<T, BS, KP, true, false, kFuse>(v, a, b, ni, rows, tab, wrow, logK, wxe, f1, f2);
+        } else {
+            if (b < 0) cterm = table_sides<T, BS, KP, false, true, kFuse>(v, a, b, ni, rows, tab, wrow, logK, wxe, f1, f2);
+            else cterm = table_sides<T, BS, KP, false, false, kFuse>(v, a, b, ni, rows, tab, wrow, logK, wxe, f1, f2);
+        }
     }
     // rows this thread owns: tid + j*BS < P
     const int nj = v.np > (int)threadIdx.x ? min(ni, (v.np - (int)threadIdx.x + BS - 1) / BS) : 0;
@@ -1032,11 +1221,29 @@ __global__ void __launch_bounds__(BS) k_optimize(const BatchArgs a, double *brle
             const int o0 = first ? td.op_first : td.op_steady;
             const int no = first ? td.n_first : td.n_steady;
             double max_rel = 0.0;
+            EdgePre pre;
+            bool have_pre = false;
             for (int o = 0; o < no; ++o) {
                 const Op op = a.ops[o0 + o];
                 if (op.code == OP_UPDATE) {
                     const long long u0 = a.prof ? clock64() : 0;
-                    do_update<T, BS, KP, kF32 ? kPmLds32 : kPmLds>(v, op, 0, ni);
+                    bool fused = false;
+                    // (FP64 partials and 256 threads per block only: with FP32
+                    // partials, or two waves per SIMD, the extra registers
+                    // made the kernel slower or spill)
+                    if constexpr (GRP && TAB_LDS && FuseFirst<KP>::value && BS == 256 && !kF32) {
+                        // an update making one side of the next edge step:
+                        // build that edge's table from it directly
+                        if (ni == 1 && o + 1 < no) {
+                            const Op nx = a.ops[o0 + o + 1];
+                            if (nx.code == OP_NEWTON && (nx.a == op.dst || nx.b == op.dst)) {
+                                pre = update_and_table<T, BS, KP, kF32 ? kPmLds32 : kPmLds>(
+                                    v, op, nx.a == op.dst ? nx.b : nx.a, tl[nx.dst], tab, wrow, wx, wxf);
+                                have_pre = fused = true;
+                            }
+                        }
+                    }
+                    if (!fused) do_update<T, BS, KP, kF32 ? kPmLds32 : kPmLds>(v, op, 0, ni);
                     if (a.prof) {
                         pc[PROF_UPDATES] += 1;
                         pc[PROF_CYC_UPDATE] += clock64() - u0;
@@ -1052,8 +1259,9 @@ __global__ void __launch_bounds__(BS) k_optimize(const BatchArgs a, double *brle
                     continue;
                 }
                 // the pass's lnL comes from its last edge step (op.ea = 1)
-                const EdgeResult r =
-                    newton_edge<T, BS, KP>(v, op.a, op.b, t0, op.ea != 0, opt, tab, wrow, ni, red, wx, wxf, parity, gs);
+                const EdgeResult r = newton_edge<T, BS, KP>(v, op.a, op.b, t0, op.ea != 0, opt, tab, wrow, ni, red, wx,
+                                                            wxf, parity, gs, have_pre ? &pre : nullptr);
+                have_pre = false;
                 parity = r.parity;
                 if (op.ea) cur = r.lnl;
                 pc[PROF_EDGE_STEPS] += 1;
