@@ -604,15 +604,17 @@ __device__ inline void table_row(const TreeView<T> &v, const SA &sa, const SB &s
 // Newton iteration, at the exponentials wxe, to f1 and f2, from the values as
 // stored and in the order of newton_rows2, so the sums are the ones a row
 // pass over the finished table would give.
-template <typename T, int BS, int KP, bool TA, bool TB, bool FUSE, typename X>
+template <typename T, int BS, int KP, bool TA, bool TB, bool FUSE, bool PAIR, typename X>
 __device__ inline double table_sides(const TreeView<T> &v, int a, int b, int ni, size_t rows, T *tab, double *wrow,
                                      double logK, const X *wxe, double &f1, double &f2) {
     const ModelS *md = v.m;
     double cterm = 0.0;
-    // two patterns per step (FP32 partials; with FP64 the registers of a
-    // second pattern would spill), both fetched before either is used; a
-    // missing second pattern re-reads the first (in bounds) and is not stored
-    constexpr int kStep = std::is_same<T, float>::value ? 2 : 1;
+    // PAIR: two patterns per step (FP32 partials; with FP64 the registers of
+    // a second pattern would spill), both fetched before either is used; a
+    // missing second pattern re-reads the first (in bounds) and is not
+    // stored.  Kernels with the fused update and table build leave PAIR off
+    // to make room for it.
+    constexpr int kStep = std::is_same<T, float>::value && PAIR ? 2 : 1;
 #pragma unroll 1
     for (int j = 0; j < ni; j += kStep) {
         const int p0 = j * BS + threadIdx.x;
@@ -866,7 +868,7 @@ __device__ inline EdgePre update_and_table(const TreeView<T> &v, const Op &op, i
     return pre;
 }
 
-template <typename T, int BS, int KP>
+template <typename T, int BS, int KP, bool PAIR = true>
 __device__ inline EdgeResult newton_edge(const TreeView<T> &v, int a, int b, double t, bool want_lnl,
                                          const OptParams &opt, T *tab, double *wrow, int ni, double *red,
                                          double *wx, float *wxf, int parity, GroupS *gs,
@@ -884,11 +886,11 @@ __device__ inline EdgeResult newton_edge(const TreeView<T> &v, int a, int b, dou
     } else {
         const auto *wxe = first_expo<T, KP>(v, t, wx, wxf);
         if (a < 0) {
-            if (b < 0) cterm = table_sides<T, BS, KP, true, true, kFuse>(v, a, b, ni, rows, tab, wrow, logK, wxe, f1, f2);
-            else cterm = table_sides<T, BS, KP, true, false, kFuse>(v, a, b, ni, rows, tab, wrow, logK, wxe, f1, f2);
+            if (b < 0) cterm = table_sides<T, BS, KP, true, true, kFuse, PAIR>(v, a, b, ni, rows, tab, wrow, logK, wxe, f1, f2);
+            else cterm = table_sides<T, BS, KP, true, false, kFuse, PAIR>(v, a, b, ni, rows, tab, wrow, logK, wxe, f1, f2);
         } else {
-            if (b < 0) cterm = table_sides<T, BS, KP, false, true, kFuse>(v, a, b, ni, rows, tab, wrow, logK, wxe, f1, f2);
-            else cterm = table_sides<T, BS, KP, false, false, kFuse>(v, a, b, ni, rows, tab, wrow, logK, wxe, f1, f2);
+            if (b < 0) cterm = table_sides<T, BS, KP, false, true, kFuse, PAIR>(v, a, b, ni, rows, tab, wrow, logK, wxe, f1, f2);
+            else cterm = table_sides<T, BS, KP, false, false, kFuse, PAIR>(v, a, b, ni, rows, tab, wrow, logK, wxe, f1, f2);
         }
     }
     // rows this thread owns: tid + j*BS < P
@@ -1180,6 +1182,7 @@ __global__ void __launch_bounds__(BS) k_optimize(const BatchArgs a, double *brle
         // FP32 partials: an FP32 copy of the matrices for the loop's updates,
         // 16-byte aligned after the lengths
         constexpr bool kF32 = std::is_same<T, float>::value;
+        constexpr bool kFuseUpd = GRP && TAB_LDS && FuseFirst<KP>::value && BS == 256;
         float *pmf = reinterpret_cast<float *>(lds + (((size_t)E * KP * 16 + E + 1) & ~(size_t)1));
         for (int e = tid; e < E; e += BS) tl[e] = fmin(fmax(brlen[td.edge_off + e], opt.t_min), opt.t_max);
         model_to_lds(aln, &model);
@@ -1228,10 +1231,9 @@ __global__ void __launch_bounds__(BS) k_optimize(const BatchArgs a, double *brle
                 if (op.code == OP_UPDATE) {
                     const long long u0 = a.prof ? clock64() : 0;
                     bool fused = false;
-                    // (FP64 partials and 256 threads per block only: with FP32
-                    // partials, or two waves per SIMD, the extra registers
-                    // made the kernel slower or spill)
-                    if constexpr (GRP && TAB_LDS && FuseFirst<KP>::value && BS == 256 && !kF32) {
+                    // (256 threads per block only: with two waves per SIMD
+                    // the extra registers would spill)
+                    if constexpr (kFuseUpd) {
                         // an update making one side of the next edge step:
                         // build that edge's table from it directly
                         if (ni == 1 && o + 1 < no) {
@@ -1259,7 +1261,7 @@ __global__ void __launch_bounds__(BS) k_optimize(const BatchArgs a, double *brle
                     continue;
                 }
                 // the pass's lnL comes from its last edge step (op.ea = 1)
-                const EdgeResult r = newton_edge<T, BS, KP>(v, op.a, op.b, t0, op.ea != 0, opt, tab, wrow, ni, red, wx,
+                const EdgeResult r = newton_edge<T, BS, KP, !kFuseUpd>(v, op.a, op.b, t0, op.ea != 0, opt, tab, wrow, ni, red, wx,
                                                             wxf, parity, gs, have_pre ? &pre : nullptr);
                 have_pre = false;
                 parity = r.parity;
