@@ -38,7 +38,9 @@ constexpr int kGroupSyncWords = 64;
 // grouped launch has kXcds * groups * ceil(trees / kXcds) blocks.
 constexpr int kXcds = 8;
 
-// Per-tree optimisation counters (when BatchArgs::prof is set).
+// Per-tree optimisation counters (when BatchArgs::prof is set).  Where an
+// edge step's last update and its table build run fused, the table's cycles
+// count as the update's.
 enum : int { PROF_PASSES, PROF_EDGE_STEPS, PROF_NEWTON_ITERS, PROF_UPDATES, PROF_CYC_UPDATE,
              PROF_CYC_TABLE, PROF_CYC_ITERS, PROF_CYC_TOTAL, PROF_FIELDS };
 
