@@ -108,9 +108,13 @@ typedef struct {
  * when a step would move t by at most tol_newton * max(t, 1e-6) (not taken),
  * or after taking a Newton step of at most max(sqrt(tol_newton), 0.03) *
  * max(t, 1e-6) (quadratic convergence; the next pass revisits the edge, and
- * the per-tree rule below bounds the final accuracy).  Per tree:
- * passes over the masked edges until a pass raises the objective by less
- * than tol_lnl and changes no length by more than tol_t relative, or
+ * the per-tree rule below bounds the final accuracy).  From a tree's second
+ * pass on, an edge whose Newton step exceeds tol_t relative moves 1.2 times
+ * that step, kept in [t_min, t_max] (nonlinear successive over-relaxation:
+ * the same maximum in fewer passes; a converged tree's last pass has no step
+ * above tol_t, so its lengths are plain Newton results).
+ * Per tree: passes over the masked edges until a pass raises the objective
+ * by less than tol_lnl and changes no length by more than tol_t relative, or
  * max_passes.
  * The objective is lnL (prior_rate = 0, maximum likelihood) or, with
  * prior_rate > 0, lnL plus the log density of independent Exponential
