@@ -155,3 +155,28 @@ def test_split_refused_when_not_resident(ctx):
         assert ei.value.code == -4
         assert plan.launch_shape() == before
     plan.close()
+
+
+def test_relaxed_steps_reach_the_oracle_optimum(ctx):
+    """From a tree's second pass on the kernel over-relaxes edge steps above
+    tol_t; the fixed point must still be the maximum the oracle's plain
+    coordinate steps reach.  At tight tolerances every C2 neighbour's FP64
+    lnL matches the stored oracle optimum far inside the default bar."""
+    aln, ne, nbl, ref = c2_batch()
+    A = pt.Alignment.from_synth(ctx, aln)
+    plan = pt.Plan(ctx, [A], pt.Trees(list(ne)), pt.PT_PLAN_OPTIMIZE, pt.PT_FP64)
+    plan.set_launch(256, 4)
+    o = pt.opt_default(pt.PT_FP64)
+    o.tol_lnl, o.tol_t, o.tol_newton, o.max_passes = 1e-10, 1e-7, 1e-11, 500
+    dev = torch.device("cuda:0")
+    b = torch.tensor(np.ravel(nbl), dtype=torch.float64, device=dev)
+    lnl = torch.zeros(len(ne), dtype=torch.float64, device=dev)
+    ps = torch.zeros(len(ne), dtype=torch.int32, device=dev)
+    st = torch.zeros(len(ne), dtype=torch.int32, device=dev)
+    plan.optimize(b, lnl, ps, st, opt=o)
+    torch.cuda.synchronize()
+    l, p, s = lnl.cpu().numpy(), ps.cpu().numpy(), st.cpu().numpy()
+    say("tight FP64: max |dlnL| %.2e, passes mean %.1f max %d" % (np.max(np.abs(l - ref)), p.mean(), p.max()))
+    assert np.all(s == 0), s
+    assert np.max(np.abs(l - ref)) < 1e-7
+    plan.close()
