@@ -274,6 +274,23 @@ def main():
             torch.cuda.synchronize()
         ms3 = e0.elapsed_time(e1) / reps
         by3 = plan3.traffic(pt.PT_PLAN_LOGLIK)
+        # the same pruning pass with FP64 partials (k_tiles64)
+        plan3d = pt.Plan(ctx, A3, T3, pt.PT_PLAN_LOGLIK, pt.PT_FP64)
+        l3d = torch.zeros_like(l3)
+        with torch.cuda.stream(stream):
+            plan3d.set_graphs(True)
+            for _ in range(3):
+                plan3d.loglik(b3, l3d, stream=stream)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(reps):
+                plan3d.loglik(b3, l3d, stream=stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+        ms3d = e0.elapsed_time(e1) / reps
+        by3d = plan3d.traffic(pt.PT_PLAN_LOGLIK)
+        d3 = float(np.max(np.abs(l3d.cpu().numpy() - l3.cpu().numpy())))
+        plan3d.close()
         # batching: all 512 topologies optimised in one persistent launch
         plan3o = pt.Plan(ctx, A3, T3, pt.PT_PLAN_OPTIMIZE, pt.PT_FP32)
         bo0 = torch.tensor(lens3, dtype=torch.float64, device=dev)
@@ -335,7 +352,11 @@ def main():
                           "achieved_GBs": round(by3 / (ms3 / 1e3) / 1e9, 1),
                           "frac_of_peak": round(by3 / (ms3 / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
                           "counter_GBs": None,
-                          "note": "graph of k_pmat + k_tiles + k_reduce"}
+                          "note": "graph of k_pmat + k_tiles + k_reduce",
+                          "fp64": {"ms_per_call": round(ms3d, 4), "algorithmic_bytes": by3d,
+                                   "achieved_GBs": round(by3d / (ms3d / 1e3) / 1e9, 1),
+                                   "frac_of_peak": round(by3d / (ms3d / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                                   "max_abs_dlnl_vs_fp32": d3}}
         if os.path.exists(TRAFFIC):
             tr = json.load(open(TRAFFIC))
             if tr.get("kernel_hash") == kernel_hash() and "tiles_512_fp32" in tr:
