@@ -92,12 +92,18 @@ struct Store<double> {
 // Model constants of the tree in flight, copied to LDS once per tree.
 struct ModelS {
     double W[16];    // W_im = pi_i U_im = Uinv_mi
+    double U[16];    // P(t) = U diag(exp(lam t)) Uinv
+    double Uinv[16];
     double lam[4];
     double rate[kMaxCats];
 };
 
 __device__ inline void model_to_lds(const AlnDev *aln, ModelS *m) {
-    for (int x = threadIdx.x; x < 16; x += blockDim.x) m->W[x] = aln->W[x];
+    for (int x = threadIdx.x; x < 16; x += blockDim.x) {
+        m->W[x] = aln->W[x];
+        m->U[x] = aln->U[x];
+        m->Uinv[x] = aln->Uinv[x];
+    }
     if (threadIdx.x < 4) m->lam[threadIdx.x] = aln->lam[threadIdx.x];
     if (threadIdx.x < kMaxCats) m->rate[threadIdx.x] = aln->rate[threadIdx.x];
 }
@@ -132,13 +138,15 @@ __device__ inline void tip_vec(unsigned code, double x[4]) {
     x[0] = code & 1u; x[1] = (code >> 1) & 1u; x[2] = (code >> 2) & 1u; x[3] = (code >> 3) & 1u;
 }
 
-// Entry (i, j) of P(r_k t) = U diag(exp(lam r_k t)) Uinv.
-__device__ inline double pm_entry(const AlnDev *aln, int k, int ij, double t) {
+// Entry (i, j) of P(r_k t) = U diag(exp(lam r_k t)) Uinv, from the block's
+// LDS copy of the model (the optimisation loop recomputes an edge's matrices
+// after every length change, and global loads there cost a round trip).
+__device__ inline double pm_entry(const ModelS *md, int k, int ij, double t) {
     const int i = ij >> 2, j = ij & 3;
-    const double r = aln->rate[k];
+    const double r = md->rate[k];
     double s = 0.0;
 #pragma unroll
-    for (int m = 0; m < 4; ++m) s += aln->U[i * 4 + m] * exp(aln->lam[m] * r * t) * aln->Uinv[m * 4 + j];
+    for (int m = 0; m < 4; ++m) s += md->U[i * 4 + m] * exp(md->lam[m] * r * t) * md->Uinv[m * 4 + j];
     return s;
 }
 
@@ -1219,7 +1227,7 @@ __global__ void __launch_bounds__(BS) k_optimize(const BatchArgs a, double *brle
         __syncthreads();
         for (int x = tid; x < E * KP * 16; x += BS) {
             const int e = x / (KP * 16), r = x % (KP * 16);
-            pm[x] = pm_entry(aln, r >> 4, r & 15, tl[e]);
+            pm[x] = pm_entry(&model, r >> 4, r & 15, tl[e]);
             if (kF32) pmf[x] = (float)pm[x];
         }
         __syncthreads();
@@ -1295,7 +1303,7 @@ __global__ void __launch_bounds__(BS) k_optimize(const BatchArgs a, double *brle
                 if (r.t != t0) {
                     if (tid == 0) tl[e] = r.t;
                     if (tid < KP * 16) {
-                        const double pe = pm_entry(aln, tid >> 4, tid & 15, r.t);
+                        const double pe = pm_entry(&model, tid >> 4, tid & 15, r.t);
                         pm[(size_t)e * KP * 16 + tid] = pe;
                         if (kF32) pmf[(size_t)e * KP * 16 + tid] = (float)pe;
                     }
