@@ -150,6 +150,16 @@ __device__ inline double pm_entry(const ModelS *md, int k, int ij, double t) {
     return s;
 }
 
+// The same entry from the exponentials ex[k*4 + m] = exp(lam_m r_k t), each
+// computed once (by the same expression) instead of once per entry.
+__device__ inline double pm_entry_ex(const ModelS *md, const double *ex, int k, int ij) {
+    const int i = ij >> 2, j = ij & 3;
+    double s = 0.0;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) s += md->U[i * 4 + m] * ex[k * 4 + m] * md->Uinv[m * 4 + j];
+    return s;
+}
+
 // 1 / x from the hardware estimate plus two Newton-Raphson steps.
 __device__ inline double recip(double x) {
     double r = __builtin_amdgcn_rcp(x);
@@ -1173,6 +1183,7 @@ __global__ void __launch_bounds__(BS) k_optimize(const BatchArgs a, double *brle
     __shared__ ModelS model;
     __shared__ int q_sh;
     __shared__ GroupS gsh;
+    __shared__ double pm_ex[4 * kMaxCats];
     const int tid = threadIdx.x;
     const int G = GRP ? a.groups : 1;
     // grouped: the hardware deals blocks to the XCDs in turn, so block i
@@ -1302,10 +1313,23 @@ __global__ void __launch_bounds__(BS) k_optimize(const BatchArgs a, double *brle
                 max_rel = fmax(max_rel, fabs(r.t - t0) / fmax(t0, 1e-6));
                 if (r.t != t0) {
                     if (tid == 0) tl[e] = r.t;
-                    if (tid < KP * 16) {
-                        const double pe = pm_entry(&model, tid >> 4, tid & 15, r.t);
-                        pm[(size_t)e * KP * 16 + tid] = pe;
-                        if (kF32) pmf[(size_t)e * KP * 16 + tid] = (float)pe;
+                    if constexpr (KP * 16 <= 64) {
+                        // the edge's matrices are one wave's work: its first
+                        // 4 KP lanes take the exponentials, then every lane
+                        // one entry (LDS operations of a wave complete in order)
+                        if (tid < 4 * KP) pm_ex[tid] = exp(model.lam[tid & 3] * model.rate[tid >> 2] * r.t);
+                        __builtin_amdgcn_wave_barrier();
+                        if (tid < KP * 16) {
+                            const double pe = pm_entry_ex(&model, pm_ex, tid >> 4, tid & 15);
+                            pm[(size_t)e * KP * 16 + tid] = pe;
+                            if (kF32) pmf[(size_t)e * KP * 16 + tid] = (float)pe;
+                        }
+                    } else {
+                        if (tid < KP * 16) {
+                            const double pe = pm_entry(&model, tid >> 4, tid & 15, r.t);
+                            pm[(size_t)e * KP * 16 + tid] = pe;
+                            if (kF32) pmf[(size_t)e * KP * 16 + tid] = (float)pe;
+                        }
                     }
                     __syncthreads();
                 }
