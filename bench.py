@@ -28,7 +28,9 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 GOLDEN = os.path.join(ROOT, "tests", "golden", "c2_hillclimb.json")
+GOLDEN3 = os.path.join(ROOT, "tests", "golden", "c3_batch512.json")
 TRAFFIC = os.path.join(ROOT, "profiles", "traffic_counters.json")
+FP64_VALU_PEAK_TFLOPS = 78.6
 
 
 def log(*a):
@@ -64,30 +66,47 @@ def key_int(k, n):
 def c3_inputs():
     """Four uneven alignments (27x1949, 36x1812, 50x1133, 64x1008), 128 NNI
     walk topologies each around the generating tree: 512 topologies."""
-    import synth
-    shapes = [(27, 1949, 31), (36, 1812, 32), (50, 1133, 33), (64, 1008, 34)]
-    alns, trees, lens, idx = [], [], [], []
-    for i, (n, S, seed) in enumerate(shapes):
-        rng = np.random.default_rng(seed)
-        e, b = synth.yule_tree(n, rng, mean=0.05)
-        alns.append(synth.make_alignment(e, b, n, S, rng, alpha=0.5, n_cats=4))
-        for te, tb in synth.nni_bfs(e, b, n, 128):
-            trees.append(te)
-            lens.append(tb)
-            idx.append(i)
-    return alns, trees, np.concatenate(lens), np.array(idx, np.int32)
+    from synth import workloads
+    return workloads.c3_inputs()
 
 
 def c4_inputs():
     """256 NNI-walk topologies of a 50-taxon x 1500-site GTR+G4 alignment with
     Exp(mean 0.05) lengths (the gradient workload)."""
-    import synth
-    rng = np.random.default_rng(4)
-    e, b = synth.yule_tree(50, rng, mean=0.05)
-    aln = synth.make_alignment(e, b, 50, 1500, rng, alpha=0.5, n_cats=4)
-    tops = [x for x, _ in synth.nni_bfs(e, b, 50, 256)]
-    lens = rng.exponential(0.05, size=(256, 97))
-    return aln, tops, lens
+    from synth import workloads
+    return workloads.c4_inputs()
+
+
+def c3_golden():
+    """Oracle lnL of the 512 topologies at their starting lengths, and the
+    local maxima the oracle reaches from three starts (the inherited lengths
+    first; tests/golden/c3_batch512.json, written by an oracle-only
+    script)."""
+    g = json.load(open(GOLDEN3))
+    return np.asarray(g["start_lnl"]), np.asarray(g["opt_lnl"]), g["local_optima"]
+
+
+def loglik_reg_flops(alns, trees, idx):
+    """Algorithmic FP64 flops of the register-resident lnL: per pattern and
+    category, each of the n-2 partial updates is two 4x4 matrix-vector
+    products and a product of the results (2*32 + 4 = 68 flops), and the root
+    edge one matrix-vector product and a weighted dot product (32 + 8)."""
+    f = 0.0
+    for t, i in zip(trees, idx):
+        a = alns[i]
+        n = a.n_taxa
+        f += a.n_patterns * a.n_cats * ((n - 2) * 68.0 + 40.0)
+    return f
+
+
+def host_cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def main():
@@ -256,41 +275,39 @@ def main():
 
         log("pruning on 512 topologies ...")
         alns3, trees3, lens3, idx3 = c3_inputs()
+        start3, same3, opt3 = c3_golden()
         A3 = [pt.Alignment.from_synth(ctx, a) for a in alns3]
         T3 = pt.Trees(trees3, idx3)
-        plan3 = pt.Plan(ctx, A3, T3, pt.PT_PLAN_LOGLIK, pt.PT_FP32)
         b3 = torch.tensor(lens3, dtype=torch.float64, device=dev)
-        l3 = torch.zeros(T3.n_trees, dtype=torch.float64, device=dev)
-        with torch.cuda.stream(stream):
-            plan3.set_graphs(True)
-            for _ in range(3):
-                plan3.loglik(b3, l3, stream=stream)
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            reps = 20
-            e0.record(stream)
-            for _ in range(reps):
-                plan3.loglik(b3, l3, stream=stream)
-            e1.record(stream)
-            torch.cuda.synchronize()
-        ms3 = e0.elapsed_time(e1) / reps
-        by3 = plan3.traffic(pt.PT_PLAN_LOGLIK)
-        # the same pruning pass with FP64 partials (k_tiles64)
-        plan3d = pt.Plan(ctx, A3, T3, pt.PT_PLAN_LOGLIK, pt.PT_FP64)
-        l3d = torch.zeros_like(l3)
-        with torch.cuda.stream(stream):
-            plan3d.set_graphs(True)
-            for _ in range(3):
-                plan3d.loglik(b3, l3d, stream=stream)
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            for _ in range(reps):
-                plan3d.loglik(b3, l3d, stream=stream)
-            e1.record(stream)
-            torch.cuda.synchronize()
-        ms3d = e0.elapsed_time(e1) / reps
-        by3d = plan3d.traffic(pt.PT_PLAN_LOGLIK)
-        d3 = float(np.max(np.abs(l3d.cpu().numpy() - l3.cpu().numpy())))
-        plan3d.close()
+        reps = 20
+
+        def time_loglik(precision, path):
+            plan = pt.Plan(ctx, A3, T3, pt.PT_PLAN_LOGLIK, precision)
+            plan.set_loglik_path(path)
+            l = torch.zeros(T3.n_trees, dtype=torch.float64, device=dev)
+            with torch.cuda.stream(stream):
+                plan.set_graphs(True)
+                for _ in range(3):
+                    plan.loglik(b3, l, stream=stream)
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                for _ in range(reps):
+                    plan.loglik(b3, l, stream=stream)
+                e1.record(stream)
+                torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            by = plan.traffic(pt.PT_PLAN_LOGLIK)
+            plan.close()
+            return ms, by, l.cpu().numpy()
+
+        # the stored post-order pass (every partial written to and read from
+        # HBM, as in an optimisation's first pass or a gradient's lower half)
+        ms3, by3, l3 = time_loglik(pt.PT_FP32, pt.PT_LOGLIK_STORED)
+        ms3d, by3d, l3d = time_loglik(pt.PT_FP64, pt.PT_LOGLIK_STORED)
+        # the register-resident pass (no partial stored)
+        ms3r, by3r, l3r = time_loglik(pt.PT_FP32, pt.PT_LOGLIK_REGISTERS)
+        flops3r = loglik_reg_flops(alns3, trees3, idx3)
+        d3 = float(np.max(np.abs(l3d - l3)))
         # batching: all 512 topologies optimised in one persistent launch
         plan3o = pt.Plan(ctx, A3, T3, pt.PT_PLAN_OPTIMIZE, pt.PT_FP32)
         bo0 = torch.tensor(lens3, dtype=torch.float64, device=dev)
@@ -313,11 +330,17 @@ def main():
             torch.cuda.synchronize()
         ms3o = f0.elapsed_time(f1) / 3
         by3o = plan3o.traffic(pt.PT_PLAN_OPTIMIZE, po.cpu().numpy())
+        lo_h = lo.cpu().numpy()
+        # distance to the nearest of the oracle's local maxima of each topology
+        d3o = np.array([min(abs(lo_h[i] - x) for x in opt3[i]) for i in range(len(opt3))])
+        ok3o = bool(np.all(d3o <= 1e-4))
         out["batched_512"] = {"workload": "512 NNI-walk topologies over 27x1949, 36x1812, 50x1133, 64x1008 "
                                           "GTR+G4, full optimisation, FP32 partials, one persistent launch",
-                              "value": round(T3.n_trees / (ms3o / 1e3), 2), "unit": "topologies/s",
+                              "value": round(T3.n_trees / (ms3o / 1e3) if ok3o else 0.0, 2), "unit": "topologies/s",
                               "ms_per_batch": round(ms3o, 3), "launch": list(shape3),
-                              "passes_mean": float(po.float().mean()),
+                              "passes_mean": float(po.float().mean()), "passes_max": int(po.max().item()),
+                              "max_abs_dlnl_vs_oracle_optimum": float(d3o.max()), "all_within_1e-4": ok3o,
+                              "at_same_start_oracle_optimum": int(np.sum(np.abs(lo_h - same3) <= 1e-4)),
                               "achieved_GBs": round(by3o / (ms3o / 1e3) / 1e9, 1)}
         plan3o.close()
         log("gradient of 256 trees ...")
@@ -347,23 +370,85 @@ def main():
                            "algorithmic_bytes": by4, "achieved_GBs": round(by4 / (ms4 / 1e3) / 1e9, 1),
                            "frac_of_peak": round(by4 / (ms4 / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
         plan4.close()
-        out["pruning"] = {"workload": "512 topologies over 27x1949, 36x1812, 50x1133, 64x1008 GTR+G4, FP32",
+        out["pruning"] = {"workload": "512 topologies over 27x1949, 36x1812, 50x1133, 64x1008 GTR+G4, FP32 "
+                                      "partials stored in HBM (the post-order pass that starts an optimisation "
+                                      "or a gradient)",
                           "ms_per_call": round(ms3, 4), "algorithmic_bytes": by3,
                           "achieved_GBs": round(by3 / (ms3 / 1e3) / 1e9, 1),
                           "frac_of_peak": round(by3 / (ms3 / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
                           "counter_GBs": None,
+                          "max_abs_dlnl_vs_oracle": float(np.max(np.abs(l3 - start3))),
                           "note": "graph of k_pmat + k_tiles + k_reduce",
                           "fp64": {"ms_per_call": round(ms3d, 4), "algorithmic_bytes": by3d,
                                    "achieved_GBs": round(by3d / (ms3d / 1e3) / 1e9, 1),
                                    "frac_of_peak": round(by3d / (ms3d / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                                   "max_rel_dlnl_vs_oracle": float(np.max(np.abs(l3d - start3) / np.abs(start3))),
                                    "max_abs_dlnl_vs_fp32": d3}}
+        d3r = np.abs(l3r - start3)
+        out["loglik_registers"] = {
+            "workload": "lnL of the same 512 topologies with no partial stored (FP64 partials of each "
+                        "pattern and category in registers and an LDS stack)",
+            "ms_per_call": round(ms3r, 4), "trees_per_s": round(T3.n_trees / (ms3r / 1e3), 1),
+            "speedup_over_stored_fp32": round(ms3 / ms3r, 2),
+            "max_abs_dlnl_vs_oracle": float(d3r.max()), "all_within_1e-4": bool(np.all(d3r <= 1e-4)),
+            "roofline": {"bound": "alu", "achieved": round(flops3r / (ms3r / 1e3) / 1e12, 3),
+                         "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": round(flops3r / (ms3r / 1e3) / 1e12 / FP64_VALU_PEAK_TFLOPS, 4),
+                         "flops_per_call": flops3r, "bytes_per_call": by3r},
+            "note": "graph of k_pmat + k_loglik_reg + k_reduce"}
+        log("threshold search, cold and warm-started ...")
+        # the learned warm start where it is meant to pay: the threshold
+        # search (T = -10, radius-0 proposals, batch 1024, FP32 partials) on
+        # the network's held-out 64-taxon x 2500-site alignment (seed 6)
+        from paper_1811_11007_amd import search as S
+        from paper_1811_11007_amd.train_warmstart import optimise_start, workload
+        e5, b5, aln5 = workload(6)
+        A5 = pt.Alignment.from_synth(ctx, aln5)
+        b5o, _ = optimise_start(ctx, A5, e5, b5)
+        warm = S.WarmStart.load(ctx, os.path.join(ROOT, "paper_1811_11007_amd", "warmstart_64x2500.json"))
+        runs = {}
+        for name, w in (("cold", None), ("warm", warm), ("cold_again", None)):
+            t0 = time.perf_counter()
+            res = S.ThresholdSearch(ctx, A5, threshold=-10.0, radius=0, warm=w, batch=1024).run([(e5, b5o)])
+            runs[name] = (time.perf_counter() - t0, res)
+        rc, rw = runs["cold_again"][1], runs["warm"][1]
+        out["search"] = {
+            "workload": "threshold search T=-10, radius-0 proposals, batch 1024, FP32 partials, held-out "
+                        "64 taxa x 2500 sites (seed 6), from the optimised generating tree",
+            "cold": {"seconds": round(runs["cold_again"][0], 3), "good": len(rc.good), "visited": rc.visited,
+                     "proposed": rc.proposed, "full_passes": rc.full_passes,
+                     "proposal_seconds": round(rc.proposal_time_s, 3), "visit_seconds": round(rc.full_time_s, 3)},
+            "warm": {"seconds": round(runs["warm"][0], 3), "good": len(rw.good), "visited": rw.visited,
+                     "proposed": rw.proposed, "full_passes": rw.full_passes,
+                     "proposal_seconds": round(rw.proposal_time_s, 3), "visit_seconds": round(rw.full_time_s, 3),
+                     "cold_redo": rw.cold_redo, "cold_better": rw.cold_better},
+            "same_good_set": set(rc.good) == set(rw.good),
+            "warm_over_cold_time": round(runs["warm"][0] / runs["cold_again"][0], 3),
+            "note": "the first cold run warms up plan memory and is not reported"}
+        log("copy bandwidth ...")
+        xc = torch.empty(1 << 28, dtype=torch.float32, device=dev)  # 1 GiB
+        yc = torch.empty_like(xc)
+        xc.fill_(1.0)
+        with torch.cuda.stream(stream):
+            for _ in range(3):
+                yc.copy_(xc)
+            c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            c0.record(stream)
+            for _ in range(10):
+                yc.copy_(xc)
+            c1.record(stream)
+            torch.cuda.synchronize()
+        msc = c0.elapsed_time(c1) / 10
+        out["copy_bandwidth"] = {"workload": "device-to-device copy of 1 GiB (torch copy_), read + write bytes",
+                                 "GBs": round(2 * xc.numel() * 4 / (msc / 1e3) / 1e9, 1),
+                                 "frac_of_peak": round(2 * xc.numel() * 4 / (msc / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
+        del xc, yc
         if os.path.exists(TRAFFIC):
             tr = json.load(open(TRAFFIC))
             if tr.get("kernel_hash") == kernel_hash() and "tiles_512_fp32" in tr:
                 # measured FETCH_SIZE + WRITE_SIZE bytes of the tile kernel over
                 # the whole graph's time (a lower bound for the kernel alone)
                 out["pruning"]["counter_GBs"] = round(tr["tiles_512_fp32"]["bytes_per_launch"] / (ms3 / 1e3) / 1e9, 1)
-        plan3.close()
 
     if not args.no_cpu:
         log("oracle cpu baseline ...")
@@ -390,7 +475,7 @@ def main():
                                          "%d threads, %.1f s" % (threads, dtn),
                                "single_thread": {"value": round(done / dt1, 4),
                                                  "sample": "first %d neighbours, %.1f s" % (done, dt1)},
-                               "host_cpus": os.cpu_count()}
+                               "host_cpus": os.cpu_count(), "host_cpu_model": host_cpu_model()}
     print(json.dumps(out), flush=True)
 
 

@@ -115,7 +115,12 @@ typedef struct {
  * above tol_t, so its lengths are plain Newton results).
  * Per tree: passes over the masked edges until a pass raises the objective
  * by less than tol_lnl and changes no length by more than tol_t relative, or
- * max_passes.
+ * max_passes; a change that starts or ends at t_min or t_max counts only
+ * when its gain by the quadratic model at the step's start (first and
+ * second derivative) is at least tol_lnl / (2n - 3), or the model is not
+ * concave there (with FP32 partials a length whose optimum is t_min would
+ * otherwise keep moving on and off the bound by noise-level amounts that
+ * change nothing).
  * The objective is lnL (prior_rate = 0, maximum likelihood) or, with
  * prior_rate > 0, lnL plus the log density of independent Exponential
  * (prior_rate) priors on every length, sum_e (log prior_rate - prior_rate
@@ -202,6 +207,25 @@ pt_status pt_plan_optimize(pt_plan *plan, double *d_brlen_inout, const pt_opt *o
 /* d_grad: device double[total edges]; d_hess NULL ok. */
 pt_status pt_plan_grad(pt_plan *plan, const double *d_brlen, double *d_lnl,
                        double *d_grad, double *d_hess, void *stream);
+
+/* Which pass computes lnL on a PT_PLAN_LOGLIK plan.
+ * PT_LOGLIK_REGISTERS (the default whenever every tree fits it): Felsenstein
+ * pruning with no partial stored in device memory -- each pattern and
+ * category keeps its partials in FP64, an accumulator in registers and a
+ * stack of at most 8 slots in LDS, filled in an order that keeps it shallow
+ * (enough for any tree of fewer than 512 taxa), and per pattern only the tip
+ * codes and the weight are read; the result is FP64 in either precision.
+ * A block needs 32 bytes per thread per stack slot plus the tile's tip codes
+ * (n bytes per pattern) within the device's LDS per block.
+ * PT_LOGLIK_STORED: the post-order pass that starts an optimisation or a
+ * gradient, storing every partial in the plan's precision (with FP32
+ * partials its lnL carries their rounding, about 1e-4 at a few thousand
+ * sites).  PT_EUNSUPPORTED for PT_LOGLIK_REGISTERS when a tree does not fit;
+ * such a plan uses the stored pass.  Gradient calls with FP32 partials
+ * report the register-resident lnL when the plan's trees fit it. */
+#define PT_LOGLIK_REGISTERS 0
+#define PT_LOGLIK_STORED 1
+pt_status pt_plan_set_loglik_path(pt_plan *plan, int32_t path);
 
 /* Time the optimisation kernel's launch shapes on this plan (lengths are
  * restored after every trial) and keep the fastest for the plan and for

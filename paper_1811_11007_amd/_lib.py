@@ -18,13 +18,14 @@ LIB_PATH = os.path.join(_HERE, "libpt.so")
 PT_OK, PT_EINVAL, PT_ENOMEM, PT_EDEVICE, PT_EUNSUPPORTED, PT_EINTERNAL = 0, -1, -2, -3, -4, -5
 PT_FP64, PT_FP32 = 0, 1
 PT_PLAN_LOGLIK, PT_PLAN_OPTIMIZE, PT_PLAN_GRAD = 1, 2, 4
+PT_LOGLIK_REGISTERS, PT_LOGLIK_STORED = 0, 1
 
 EXPORTS = [
     "pt_last_error", "pt_ctx_create", "pt_ctx_destroy", "pt_aln_create", "pt_aln_destroy",
     "pt_opt_default", "pt_batch_loglik", "pt_batch_optimize_branches", "pt_batch_branch_grad",
     "pt_plan_create", "pt_plan_destroy", "pt_plan_set_graphs", "pt_plan_loglik",
     "pt_plan_optimize", "pt_plan_set_alpha", "pt_plan_optimize_alpha", "pt_plan_grad", "pt_plan_autotune",
-    "pt_plan_traffic", "pt_plan_set_profile", "pt_plan_info", "pt_plan_set_launch", "pt_plan_launch_shape",
+    "pt_plan_traffic", "pt_plan_set_profile", "pt_plan_set_loglik_path", "pt_plan_info", "pt_plan_set_launch", "pt_plan_launch_shape",
     "pt_model_info", "pt_tree_check", "pt_nni_neighbors", "pt_topology_key", "pt_topology_keys",
     "pt_nni_features", "pt_radius_masks", "pt_split_frequencies", "pt_majority_consensus",
     "pt_mlp_create", "pt_mlp_destroy", "pt_mlp_param_count", "pt_mlp_get_params", "pt_mlp_set_params",
@@ -112,6 +113,7 @@ def lib():
         L.pt_plan_info.argtypes = [vp, P(i32), P(i64), P(i64)]
         L.pt_plan_traffic.argtypes = [vp, i32, vp, P(ctypes.c_double)]
         L.pt_plan_set_profile.argtypes = [vp, vp]
+        L.pt_plan_set_loglik_path.argtypes = [vp, i32]
         L.pt_model_info.argtypes = [P(pt_model), vp, vp, vp, vp]
         L.pt_tree_check.argtypes = [i32, vp]
         L.pt_nni_neighbors.argtypes = [i32, vp, vp, vp, vp, vp]
@@ -496,6 +498,10 @@ class Plan:
     def set_launch(self, block, groups=1):
         """Optimisation kernel shape: threads per block, blocks per tree."""
         check(lib().pt_plan_set_launch(self.h, int(block), int(groups)))
+
+    def set_loglik_path(self, path):
+        """PT_LOGLIK_REGISTERS (default) or PT_LOGLIK_STORED; see pt.h."""
+        check(lib().pt_plan_set_loglik_path(self.h, int(path)))
 
     def launch_shape(self):
         """(threads per block, patterns per thread, blocks per tree)."""

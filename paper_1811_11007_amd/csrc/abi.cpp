@@ -44,8 +44,6 @@ pt_status fail(pt_status st, const std::string &msg) {
                         std::string(#call) + ": " + hipGetErrorString(e_));                    \
     } while (0)
 
-// LDS the kernels may use for the per-tree transition matrix cache.
-constexpr size_t kLdsBudget = 64 * 1024;
 constexpr int kMaxOptPatterns = 512 * 64;
 
 int64_t arena_cap() {
@@ -105,6 +103,16 @@ struct pt_plan {
     Op *d_ops = nullptr;
     TreeDev *d_trees_ll = nullptr, *d_trees_gr = nullptr, *d_trees_opt = nullptr;
     int32_t *d_tile_tree = nullptr, *d_edge_tree = nullptr, *d_order = nullptr, *d_queue = nullptr;
+    // the register-resident lnL (k_loglik_reg): its descriptors, tiles and
+    // tile sums; reg_ok when every tree of the plan fits it
+    bool reg_ok = false, stored_ok = true;
+    int ll_stored = 0;  // pt_plan_set_loglik_path: 1 = the stored post-order pass
+    TreeDev *d_trees_reg = nullptr;
+    int32_t *d_tile_tree_reg = nullptr;
+    double *d_part_reg = nullptr;
+    int n_tiles_reg = 0, reg_depth = 0;
+    size_t lds_reg = 0;
+    const double *ident = nullptr;  // the 4x4 identity, after the matrices
     void *d_clv = nullptr;
     uint16_t *d_cnt = nullptr;
     double *d_pmat = nullptr, *d_part = nullptr, *d_scratch = nullptr;
@@ -123,7 +131,7 @@ struct pt_plan {
     std::shared_ptr<DevicePool> pool;                // where they go when the plan is destroyed
     // host copies for traffic accounting
     std::vector<Op> ops_h;
-    std::vector<TreeDev> tll_h, tgr_h, top_h;
+    std::vector<TreeDev> tll_h, tgr_h, top_h, treg_h;
     std::vector<AlnDev> alns_h;       // per tree, as on the device
     std::vector<AlnDev> alns_base_h;  // per tree, the alignment's own model
     double *d_alpha_lnl = nullptr;    // per tree, for the Gamma-shape search
@@ -280,6 +288,20 @@ int64_t tree_bytes(int n, const AlnDev &a, int precision, int kinds) {
 // per-wave exponential tables, model, counter), rounded up.
 constexpr size_t kOptStaticLds = 12288;
 
+// Doubles of the optimisation kernel's per-tree LDS before its table: with
+// FP64 partials the FP64 matrices then the lengths; with FP32 partials the
+// lengths then (16-byte aligned) an FP32 copy of the matrices.
+size_t opt_pm_doubles(int precision, int E, int kp) {
+    return precision == PT_FP32 ? (((size_t)E + 1) & ~(size_t)1) + (size_t)E * kp * 8
+                                : (size_t)E * (kp * 16 + 1);
+}
+
+// LDS of the stored post-order pass for one tree: FP64 partials read the
+// matrices from an LDS copy, FP32 partials by scalar loads (none).
+size_t stored_lds(int precision, int E, int kp) {
+    return precision == PT_FP64 ? (size_t)E * kp * 16 * 8 : 0;
+}
+
 // Sets the optimisation launch shape for `block` threads per block: patterns
 // per thread, where the eigenbasis table lives (LDS when it fits, else a
 // per-block global buffer), dynamic LDS, grid.  Refuses shapes whose kernel
@@ -380,10 +402,11 @@ pt_status plan_build(pt_ctx *ctx, pt_aln *const *alns, int32_t n_alns, const pt_
     struct Compiled {
         pt_status st = PT_OK;
         std::string err;
-        int E = 0, n_slots = 0;
-        bool any = true;
-        std::vector<Op> ll, gr, p1, p2, p3;
+        int E = 0, n_slots = 0, reg_depth = 0;
+        bool any = true, stored_ok = true;
+        std::vector<Op> ll, gr, p1, p2, p3, rg;
     };
+    const bool want_reg = (kinds & PT_PLAN_LOGLIK) || ((kinds & PT_PLAN_GRAD) && precision == PT_FP32);
     std::vector<Compiled> cp(B);
     auto compile_tree = [&](int b) {
         Compiled &c = cp[b];
@@ -395,10 +418,18 @@ pt_status plan_build(pt_ctx *ctx, pt_aln *const *alns, int32_t n_alns, const pt_
         if (c.st) { c.err = "tree " + std::to_string(b) + ": " + err; return; }
         c.E = t.n_edges;
         c.n_slots = t.n_slots();
-        if ((size_t)c.E * kp * 16 * 8 + (size_t)c.E * 8 > kLdsBudget) {
+        // transition matrices the kernels keep in LDS, per tree
+        if ((kinds & PT_PLAN_OPTIMIZE) && opt_pm_doubles(precision, c.E, kp) * 8 + kOptStaticLds > ctx->lds_per_block) {
             c.st = PT_EUNSUPPORTED;
-            c.err = "tree " + std::to_string(b) + ": (2n-3) * padded categories exceeds the 64 KiB "
-                    "transition-matrix cache (at most 504 edge-categories)";
+            c.err = "tree " + std::to_string(b) + ": (2n-3) x padded categories transition matrices exceed the "
+                    "LDS of a block for branch optimisation (" + std::to_string(ctx->lds_per_block) + " bytes)";
+            return;
+        }
+        c.stored_ok = stored_lds(precision, c.E, kp) <= ctx->lds_per_block;
+        if ((kinds & PT_PLAN_GRAD) && !c.stored_ok) {
+            c.st = PT_EUNSUPPORTED;
+            c.err = "tree " + std::to_string(b) + ": (2n-3) x padded categories FP64 transition matrices exceed the "
+                    "LDS of a block (" + std::to_string(ctx->lds_per_block) + " bytes)";
             return;
         }
         if ((kinds & PT_PLAN_OPTIMIZE) && ad.P > kMaxOptPatterns) {
@@ -406,6 +437,7 @@ pt_status plan_build(pt_ctx *ctx, pt_aln *const *alns, int32_t n_alns, const pt_
             c.err = "tree " + std::to_string(b) + ": more than 32768 patterns for branch optimisation";
             return;
         }
+        if (want_reg) c.reg_depth = pt::compile_loglik_reg(t, c.rg);
         if (kinds & PT_PLAN_LOGLIK) pt::compile_loglik(t, c.ll);
         if (kinds & PT_PLAN_GRAD) pt::compile_grad(t, c.gr);
         if (kinds & PT_PLAN_OPTIMIZE) {
@@ -433,6 +465,24 @@ pt_status plan_build(pt_ctx *ctx, pt_aln *const *alns, int32_t n_alns, const pt_
     }
     for (int b = 0; b < B; ++b)
         if (cp[b].st) return fail(cp[b].st, cp[b].err);
+    // the register-resident lnL needs every tree within its stack and the
+    // tile's tip codes within the LDS of a block
+    const int reg_pats = pt::loglik_reg_tile_patterns(kp);
+    pl->reg_ok = want_reg && B > 0;
+    int reg_depth = 0, reg_n = 0;
+    for (int b = 0; b < B; ++b) {
+        reg_depth = std::max(reg_depth, cp[b].reg_depth);
+        reg_n = std::max(reg_n, ntx[b]);
+    }
+    if (reg_depth > pt::kRegStack || pt::loglik_reg_lds(kp, reg_n, reg_depth) > ctx->lds_per_block)
+        pl->reg_ok = false;
+    pl->reg_depth = reg_depth;
+    pl->stored_ok = true;
+    for (int b = 0; b < B; ++b) pl->stored_ok = pl->stored_ok && cp[b].stored_ok;
+    if ((kinds & PT_PLAN_LOGLIK) && !pl->reg_ok && !pl->stored_ok)
+        return fail(PT_EUNSUPPORTED, "a tree exceeds the LDS of a block on both likelihood passes");
+    if (!pl->reg_ok) pl->ll_stored = 1;
+    std::vector<TreeDev> treg(B);
     for (int b = 0; b < B; ++b) {
         Compiled &c = cp[b];
         const AlnDev &ad = alns[trees->aln_index[b]]->desc;
@@ -460,6 +510,11 @@ pt_status plan_build(pt_ctx *ctx, pt_aln *const *alns, int32_t n_alns, const pt_
             count = (int32_t)v.size();
             ops.insert(ops.end(), v.begin(), v.end());
         };
+        if (pl->reg_ok) {
+            treg[b] = base;
+            treg[b].n_tiles = (ad.P + reg_pats - 1) / reg_pats;
+            append(c.rg, treg[b].op_first, treg[b].n_first);
+        }
         if (kinds & PT_PLAN_LOGLIK) append(c.ll, tll[b].op_first, tll[b].n_first);
         if (kinds & PT_PLAN_GRAD) append(c.gr, tgr[b].op_first, tgr[b].n_first);
         if (kinds & PT_PLAN_OPTIMIZE) {
@@ -473,6 +528,20 @@ pt_status plan_build(pt_ctx *ctx, pt_aln *const *alns, int32_t n_alns, const pt_
         std::vector<Op>().swap(c.p1);
         std::vector<Op>().swap(c.p2);
         std::vector<Op>().swap(c.p3);
+        std::vector<Op>().swap(c.rg);
+    }
+    std::vector<int32_t> tile_tree_reg;
+    if (pl->reg_ok) {
+        // register tiles of the longest programs first, as below
+        std::vector<int> order(B);
+        for (int b = 0; b < B; ++b) order[b] = b;
+        std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return pl->tree_E[x] > pl->tree_E[y]; });
+        for (int b : order) {
+            treg[b].tile_begin = (int32_t)tile_tree_reg.size();
+            for (int x = 0; x < treg[b].n_tiles; ++x) tile_tree_reg.push_back(b);
+        }
+        pl->lds_reg = pt::loglik_reg_lds(kp, reg_n, reg_depth);
+        pl->n_tiles_reg = (int)tile_tree_reg.size();
     }
     if (kinds & (PT_PLAN_LOGLIK | PT_PLAN_GRAD)) {
         // Tiles of the trees with the longest programs first: the hardware
@@ -492,13 +561,14 @@ pt_status plan_build(pt_ctx *ctx, pt_aln *const *alns, int32_t n_alns, const pt_
     pl->tll_h = tll;
     pl->tgr_h = tgr;
     pl->top_h = top;
+    pl->treg_h = treg;
     for (int b = 0; b < B; ++b) pl->alns_h.push_back(alns[trees->aln_index[b]]->desc);
     pl->alns_base_h = pl->alns_h;
 
     // arena cap
-    int64_t need = clv_off * (int64_t)store_bytes(precision) + cnt_off * 2 + pm_off * 8 +
+    int64_t need = clv_off * (int64_t)store_bytes(precision) + cnt_off * 2 + (pm_off + 16) * 8 +
                    (int64_t)ops.size() * sizeof(Op) + (int64_t)tiles * std::max(1, pl->max_E) * 24 +
-                   (int64_t)NE * 16 + (int64_t)B * 3 * sizeof(TreeDev);
+                   (int64_t)NE * 16 + (int64_t)B * 4 * sizeof(TreeDev) + (int64_t)pl->n_tiles_reg * 28;
     int64_t cap = arena_cap();
     if (cap > 0 && need > cap)
         return fail(PT_ENOMEM, "batch needs " + std::to_string(need) + " device bytes, over PT_ARENA_CAP_BYTES");
@@ -520,6 +590,13 @@ pt_status plan_build(pt_ctx *ctx, pt_aln *const *alns, int32_t n_alns, const pt_
     if (kinds & PT_PLAN_LOGLIK) if ((st = up_trees(tll, &pl->d_trees_ll))) return st;
     if (kinds & PT_PLAN_GRAD) if ((st = up_trees(tgr, &pl->d_trees_gr))) return st;
     if (kinds & PT_PLAN_OPTIMIZE) if ((st = up_trees(top, &pl->d_trees_opt))) return st;
+    if (pl->reg_ok) {
+        if ((st = up_trees(treg, &pl->d_trees_reg))) return st;
+        if ((st = dev_alloc(pl.get(), &pl->d_tile_tree_reg, sizeof(int32_t) * pl->n_tiles_reg))) return st;
+        PT_HIP(hipMemcpy(pl->d_tile_tree_reg, tile_tree_reg.data(), sizeof(int32_t) * pl->n_tiles_reg,
+                         hipMemcpyHostToDevice));
+        if ((st = dev_alloc(pl.get(), &pl->d_part_reg, sizeof(double) * 3 * (size_t)pl->n_tiles_reg))) return st;
+    }
     if ((st = dev_alloc(pl.get(), &pl->d_edge_tree, sizeof(int32_t) * std::max<int64_t>(1, NE)))) return st;
     if (NE) PT_HIP(hipMemcpy(pl->d_edge_tree, edge_tree.data(), sizeof(int32_t) * NE, hipMemcpyHostToDevice));
     if (tiles) {
@@ -538,7 +615,14 @@ pt_status plan_build(pt_ctx *ctx, pt_aln *const *alns, int32_t n_alns, const pt_
     }
     if ((st = dev_alloc(pl.get(), &pl->d_clv, (size_t)clv_off * store_bytes(precision)))) return st;
     if ((st = dev_alloc(pl.get(), &pl->d_cnt, (size_t)cnt_off * 2))) return st;
-    if ((st = dev_alloc(pl.get(), &pl->d_pmat, (size_t)pm_off * 8))) return st;
+    // the trees' matrices, then the 4x4 identity the register-resident pass
+    // applies to one side at the root edge
+    if ((st = dev_alloc(pl.get(), &pl->d_pmat, (size_t)(pm_off + 16) * 8))) return st;
+    {
+        const double ident[16] = {1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1};
+        PT_HIP(hipMemcpy(pl->d_pmat + pm_off, ident, sizeof(ident), hipMemcpyHostToDevice));
+    }
+    pl->ident = pl->d_pmat + pm_off;
     PT_HIP(hipSetDevice(dev_prev));
 
     pl->lds_tiles = 0;
@@ -546,11 +630,7 @@ pt_status plan_build(pt_ctx *ctx, pt_aln *const *alns, int32_t n_alns, const pt_
         const AlnDev &a2 = alns[trees->aln_index[b]]->desc;
         (void)a2;
         pl->lds_tiles = std::max(pl->lds_tiles, (size_t)pl->tree_E[b] * kp * 16 * 8);
-        // matrices and lengths, then (FP32 partials) an FP32 copy of the
-        // matrices on a 16-byte boundary
-        const int E = pl->tree_E[b];
-        const int dbl = E * (kp * 16 + 1);
-        pl->pm_doubles = std::max(pl->pm_doubles, precision == PT_FP32 ? ((dbl + 1) & ~1) + E * kp * 8 : dbl);
+        pl->pm_doubles = std::max(pl->pm_doubles, (int)opt_pm_doubles(precision, pl->tree_E[b], kp));
     }
     pl->pm_doubles = (pl->pm_doubles + 3) / 4 * 4;  // 32-byte aligned table rows after it
     if (kinds & PT_PLAN_OPTIMIZE) {
@@ -602,10 +682,27 @@ pt_status enqueue(pt_plan *pl, int kind, const double *brlen_c, double *brlen, c
     hipError_t e = hipSuccess;
     if (kind == PT_PLAN_LOGLIK || kind == PT_PLAN_GRAD) {
         const bool g = kind == PT_PLAN_GRAD;
+        const bool reg_ll = !g && pl->reg_ok && !pl->ll_stored;
         pt::BatchArgs a = batch_args(pl, g ? pl->d_trees_gr : pl->d_trees_ll, g ? std::max(1, pl->max_E) : 1);
         if ((e = pt::launch_pmat(a, brlen_c, s)) != hipSuccess) goto bad;
-        if ((e = pt::launch_tiles(pl->precision, pl->kp, a, brlen_c, pl->lds_tiles, s)) != hipSuccess) goto bad;
-        if ((e = pt::launch_reduce(g, a, lnl, grad, hess, s)) != hipSuccess) goto bad;
+        if (!reg_ll) {
+            if ((e = pt::launch_tiles(pl->precision, pl->kp, a, brlen_c, pl->lds_tiles, s)) != hipSuccess) goto bad;
+            if ((e = pt::launch_reduce(g, a, lnl, grad, hess, s)) != hipSuccess) goto bad;
+        }
+        // lnL with every partial in FP64 registers: the likelihood call
+        // itself, and the lnL a gradient call with FP32 partials reports
+        // (FP32 storage puts ~1e-4 of rounding noise into lnL at a few
+        // thousand sites; the gradient keeps its stored partials)
+        if (reg_ll || (g && pl->reg_ok && pl->precision == PT_FP32)) {
+            pt::BatchArgs r = batch_args(pl, pl->d_trees_reg, 1);
+            r.tile_tree = pl->d_tile_tree_reg;
+            r.part = pl->d_part_reg;
+            r.n_tiles = pl->n_tiles_reg;
+            r.reg_depth = pl->reg_depth;
+            r.ident = pl->ident;
+            if ((e = pt::launch_loglik_reg(pl->kp, r, pl->lds_reg, s)) != hipSuccess) goto bad;
+            if (lnl && (e = pt::launch_reduce(false, r, lnl, nullptr, nullptr, s)) != hipSuccess) goto bad;
+        }
         return PT_OK;
     }
     {
@@ -1039,6 +1136,19 @@ pt_status pt_plan_set_launch(pt_plan *plan, int32_t block, int32_t groups) {
     return PT_OK;
 }
 
+pt_status pt_plan_set_loglik_path(pt_plan *plan, int32_t path) {
+    if (!plan || !(plan->kinds & PT_PLAN_LOGLIK)) return fail(PT_EINVAL, "plan was not created with PT_PLAN_LOGLIK");
+    if (path != PT_LOGLIK_REGISTERS && path != PT_LOGLIK_STORED) return fail(PT_EINVAL, "unknown lnL path");
+    if (path == PT_LOGLIK_REGISTERS && plan->n_trees > 0 && !plan->reg_ok)
+        return fail(PT_EUNSUPPORTED, "a tree of this plan exceeds the register-resident pass (stack or tip tile)");
+    if (path == PT_LOGLIK_STORED && plan->n_trees > 0 && !plan->stored_ok)
+        return fail(PT_EUNSUPPORTED, "a tree of this plan exceeds the LDS of the stored pass");
+    plan->ll_stored = path == PT_LOGLIK_STORED;
+    for (auto &kv : plan->execs) (void)hipGraphExecDestroy(kv.second);
+    plan->execs.clear();
+    return PT_OK;
+}
+
 pt_status pt_plan_launch_shape(const pt_plan *plan, int32_t *block, int32_t *items, int32_t *groups) {
     if (!plan) return fail(PT_EINVAL, "plan is NULL");
     if (block) *block = plan->opt_block;
@@ -1235,6 +1345,15 @@ pt_status pt_plan_traffic(const pt_plan *plan, int32_t kind, const int32_t *pass
     const std::vector<TreeDev> &tv = kind == PT_PLAN_LOGLIK ? plan->tll_h : kind == PT_PLAN_GRAD ? plan->tgr_h : plan->top_h;
     const double b = (double)store_bytes(plan->precision);
     double total = 0.0;
+    if (kind == PT_PLAN_LOGLIK && plan->reg_ok && !plan->ll_stored) {
+        // register-resident pass: every tip code and weight once per pattern
+        for (int t = 0; t < plan->n_trees; ++t) {
+            const AlnDev &a = plan->alns_h[tv[t].aln];
+            total += (double)a.P * (a.n_taxa + 8);
+        }
+        *bytes_out = total;
+        return PT_OK;
+    }
     for (int t = 0; t < plan->n_trees; ++t) {
         const AlnDev &a = plan->alns_h[tv[t].aln];
         const double slot = (double)a.P * a.K * 4 * b + (double)a.P * 2, tip = (double)a.P;

@@ -221,67 +221,100 @@ __device__ inline void block_sum3(double &a, double &b, double &c, double *red, 
 }
 
 // A tree optimised by G > 1 blocks, each over its own share of the patterns
-// (k_optimize): every block sum is combined across the blocks.  Thread 0 of
-// each block exchanges its triple into its own entry of one of two
-// alternating slots, counts its arrival, waits for all G arrivals of this
-// reduction, and reads the G triples back, summing them in block order, so
-// that every block holds the same totals and takes the same decisions.  All
-// of these accesses are device-scope atomics (exchanges and adds, and
-// device-scope atomic loads), coherent across the XCDs, and each is issued
-// only after the previous one returned, so no cache maintenance is needed.
-// (The blocks' own partials are a different matter: see k_optimize.)  A slot is rewritten two
-// reductions later, by when every block has read it (each block reads it
-// before arriving at the next reduction).  A wait is bounded in time: when
-// it runs out the tree is marked broken, its blocks stop waiting, and its
-// status reports the failure.
-// per-tree words (kGroupSyncWords): arrive, broken, then slots [2][G][3]
-static_assert(2 + 2 * kGroupBlocksMax * 3 <= kGroupSyncWords, "cross-block state does not fit");
+// (k_optimize): every block sum is combined across the blocks.  Lane 0 of
+// each block's first wave publishes the block's triple in its own entry of
+// one of two alternating slots, each value carrying the reduction's number
+// (mod 4) in its two lowest mantissa bits; lanes 0..G-1 of that wave then
+// poll the G entries in parallel, one entry per lane, until every value of
+// every entry carries the number, and the G triples are summed in block
+// order with the tag bits cleared.  Every block sums the same bits in the
+// same order, so all hold identical totals and take identical decisions;
+// clearing the two bits perturbs a value by at most 2^-51 relative.  One
+// store and one load round trip per reduction, with no counter.  The
+// accesses are device-scope atomics (coherent across the XCDs).  A slot is
+// rewritten two reductions later, by when every block has read it (a block
+// publishes reduction s + 1 only after reading all of s), and the previous
+// content of a slot carries another number (or is zero, which no reduction
+// uses as its tag).  A wait is bounded in time: when it runs out the tree is
+// marked broken, its blocks stop waiting, and its status reports the failure.
+// (The blocks' own partials are a different matter: see k_optimize.)
+// per-tree words (kGroupSyncWords): broken, then slots [2][G][3]
+static_assert(1 + 2 * kGroupBlocksMax * 3 <= kGroupSyncWords, "cross-block state does not fit");
 constexpr long long kGroupWaitCycles = 1ll << 27;  // shader clocks before a wait gives up
 
 __device__ inline unsigned long long load_agent(unsigned long long *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-struct GroupS {  // in LDS; thread 0 of the block alone uses the fields below G / g
+__device__ inline void store_agent(unsigned long long *p, unsigned long long v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ inline unsigned long long tag_bits(double v, unsigned long long tag) {
+    return ((unsigned long long)__double_as_longlong(v) & ~3ull) | tag;
+}
+
+__device__ inline double untag(unsigned long long b) { return __longlong_as_double((long long)(b & ~3ull)); }
+
+__device__ inline unsigned long long lane_u64(unsigned long long v, int lane) {
+    const unsigned lo = __builtin_amdgcn_readlane((unsigned)v, lane);
+    const unsigned hi = __builtin_amdgcn_readlane((unsigned)(v >> 32), lane);
+    return ((unsigned long long)hi << 32) | lo;
+}
+
+struct GroupS {  // in LDS; written by lane 0 of the block's first wave
     int G, g;
     int seq, is_broken;
-    unsigned long long *arrive, *broken, *slots;
+    unsigned long long *broken, *slots;
     double tot[3];
 };
 
+// Called by the block's first wave (all 64 lanes) with the block's totals.
 __device__ inline void group_exchange(GroupS *gs, double a, double b, double c) {
-    const int G = gs->G, s = gs->seq;
+    const int G = gs->G, g = gs->g, s = gs->seq;
+    const int lane = threadIdx.x & 63;
     unsigned long long *slot = gs->slots + (size_t)(s & 1) * G * 3;
-    unsigned long long *mine = slot + gs->g * 3;
-    const unsigned long long o0 = atomicExch(mine + 0, (unsigned long long)__double_as_longlong(a));
-    const unsigned long long o1 = atomicExch(mine + 1, (unsigned long long)__double_as_longlong(b));
-    const unsigned long long o2 = atomicExch(mine + 2, (unsigned long long)__double_as_longlong(c));
-    // the arrival is issued once the three exchanges have returned
-    asm volatile("" : : "v"(o0), "v"(o1), "v"(o2) : "memory");
-    atomicAdd(gs->arrive, 1ull);
-    const unsigned long long target = (unsigned long long)G * (unsigned long long)(s + 1);
+    const unsigned long long want = (unsigned long long)((s + 1) & 3);
+    const unsigned long long ta = tag_bits(a, want), tb = tag_bits(b, want), tc = tag_bits(c, want);
+    if (lane == 0) {
+        store_agent(slot + g * 3 + 0, ta);
+        store_agent(slot + g * 3 + 1, tb);
+        store_agent(slot + g * 3 + 2, tc);
+    }
+    unsigned long long va = ta, vb = tb, vc = tc;  // lane g keeps its own entry
+    bool ok = lane >= G || lane == g;
     if (!gs->is_broken) {
         const long long t0 = clock64();
-        while (load_agent(gs->arrive) < target) {
+        for (;;) {
+            if (!ok) {
+                va = load_agent(slot + lane * 3 + 0);
+                vb = load_agent(slot + lane * 3 + 1);
+                vc = load_agent(slot + lane * 3 + 2);
+                ok = (va & 3ull) == want && (vb & 3ull) == want && (vc & 3ull) == want;
+            }
+            if (__all(ok)) break;
             if (clock64() - t0 > kGroupWaitCycles) {
-                atomicExch(gs->broken, 1ull);
-                gs->is_broken = 1;
+                if (lane == 0) {
+                    store_agent(gs->broken, 1ull);
+                    gs->is_broken = 1;
+                }
                 break;
             }
             __builtin_amdgcn_s_sleep(1);
         }
     }
-    asm volatile("" : : : "memory");
     double t0 = 0.0, t1 = 0.0, t2 = 0.0;
     for (int h = 0; h < G; ++h) {
-        t0 += __longlong_as_double((long long)load_agent(slot + h * 3 + 0));
-        t1 += __longlong_as_double((long long)load_agent(slot + h * 3 + 1));
-        t2 += __longlong_as_double((long long)load_agent(slot + h * 3 + 2));
+        t0 += untag(lane_u64(va, h));
+        t1 += untag(lane_u64(vb, h));
+        t2 += untag(lane_u64(vc, h));
     }
-    gs->tot[0] = t0;
-    gs->tot[1] = t1;
-    gs->tot[2] = t2;
-    gs->seq = s + 1;
+    if (lane == 0) {
+        gs->tot[0] = t0;
+        gs->tot[1] = t1;
+        gs->tot[2] = t2;
+        gs->seq = s + 1;
+    }
 }
 
 // Block sum of three values, then (gs set) the sum over the tree's blocks;
@@ -290,7 +323,7 @@ template <int BS>
 __device__ inline void group_sum3(double &a, double &b, double &c, double *red, int &parity, GroupS *gs) {
     block_sum3<BS>(a, b, c, red, parity);
     if (gs == nullptr) return;
-    if (threadIdx.x == 0) group_exchange(gs, a, b, c);
+    if (threadIdx.x < 64) group_exchange(gs, a, b, c);
     __syncthreads();
     a = gs->tot[0];
     b = gs->tot[1];
@@ -356,7 +389,9 @@ struct Side {
 //             to every lane;
 //   kPmLds32  FP32 copy in LDS (half the broadcast bytes), for FP32 partials
 //             in the optimisation loop.
-enum : int { kPmLds = 0, kPmConst = 1, kPmLds32 = 2 };
+//   kPmGlobal FP64 matrices in global memory (the FP64 evaluation that ends
+//             an optimisation with FP32 partials).
+enum : int { kPmLds = 0, kPmConst = 1, kPmLds32 = 2, kPmGlobal = 3 };
 template <int PM>
 struct PmPtr {
     using type = const double *;
@@ -368,6 +403,10 @@ struct PmPtr<kPmConst> {
 template <>
 struct PmPtr<kPmLds32> {
     using type = const float *;
+};
+template <>
+struct PmPtr<kPmGlobal> {
+    using type = const __attribute__((address_space(1))) double *;
 };
 template <int PM, typename V>
 __device__ inline typename PmPtr<PM>::type pm_base(const V &v) {
@@ -569,6 +608,7 @@ __device__ inline Sums3 eval_edge(const TreeView<T> &v, int a, int b, int base, 
 
 struct EdgeResult {
     double t, lnl;
+    double gain;  // the objective's gain from the step by its quadratic model at the start, or +inf
     int parity, iters;
     long long cyc_table, cyc_iters;
 };
@@ -933,6 +973,7 @@ __device__ inline EdgeResult newton_edge(const TreeView<T> &v, int a, int b, dou
     const int nj = v.np > (int)threadIdx.x ? min(ni, (v.np - (int)threadIdx.x + BS - 1) / BS) : 0;
     const long long c1 = clock64();
     double lo = opt.t_min, hi = opt.t_max;
+    double d1_0 = 0.0, d2_0 = 0.0;  // derivatives at the starting length
     int iter = 1;
     for (;; ++iter) {
         double d0 = 0.0, d1 = 0.0, d2 = 0.0;
@@ -958,6 +999,10 @@ __device__ inline EdgeResult newton_edge(const TreeView<T> &v, int a, int b, dou
         }
         group_sum3<BS>(d0, d1, d2, red, parity, gs);
         d1 -= opt.prior_rate;  // MAP: the exponential prior's log density is linear in t
+        if (iter == 1) {
+            d1_0 = d1;
+            d2_0 = d2;
+        }
         if (iter >= opt.max_newton) break;
         if (d1 > 0.0) lo = t;
         else if (d1 < 0.0) hi = t;
@@ -1000,6 +1045,10 @@ __device__ inline EdgeResult newton_edge(const TreeView<T> &v, int a, int b, dou
     r.iters = iter;
     r.cyc_table = c1 - c0;
     r.cyc_iters = clock64() - c1;
+    {
+        const double dt = t - t_in;
+        r.gain = d2_0 < 0.0 ? d1_0 * dt + 0.5 * d2_0 * dt * dt : INFINITY;
+    }
     return r;
 }
 
@@ -1146,6 +1195,175 @@ __global__ void k_reduce(const BatchArgs a, bool grad, double *lnl, double *gout
     if (e == 0 && lnl) lnl[b] = s0;
 }
 
+// ------------------------------------------------ register-resident lnL
+//
+// The lnL of a tree by Felsenstein's post-order pass with no partial ever
+// stored: a lane owns one pattern and one rate category, and its partials
+// live in registers (an accumulator and a stack of kRegStack slots, the
+// program ordered so that the stack stays shallow, see compile_loglik_reg).
+// A wave is one category of 64 patterns, so every transition-matrix entry
+// it reads is wave-uniform and arrives by scalar loads (k_pmat writes the
+// matrices before the launch).  Arithmetic is FP64 whatever the storage
+// precision of the plan, because nothing is stored.  Scaling is per lane
+// (per pattern and category): a partial whose largest entry falls below
+// 2^-256 is multiplied by 2^256 and the lane counts the event; all events of
+// a lane multiply into its root value, so one counter per lane suffices.
+// At the root edge the categories of a pattern meet in LDS:
+//   ln L_p = ln sum_k 2^(-256 (c_k - c_min)) L_k - ln K - 256 c_min ln 2.
+// Memory traffic per pattern: the n tip codes and the weight.
+template <int KP>
+struct RegShape {
+    static constexpr int kWaves = KP >= 4 ? KP : 4;        // waves per block
+    static constexpr int kGroups = kWaves / KP;             // 64-pattern groups per block
+    static constexpr int kPats = 64 * kGroups;              // patterns per tile
+    static constexpr int kThreads = 64 * kWaves;
+};
+
+__device__ inline void reg_copy(double d[4], const double s[4]) {
+    d[0] = s[0]; d[1] = s[1]; d[2] = s[2]; d[3] = s[3];
+}
+
+// The stack lives in LDS, [slot][thread] of four doubles (a stack indexed by
+// a runtime slot number does not stay in registers); the accumulator, which
+// most steps read and write, is in registers.
+template <int KP>
+__global__ void __launch_bounds__(RegShape<KP>::kThreads) k_loglik_reg(const BatchArgs a) {
+    using RS = RegShape<KP>;
+    // dynamic LDS: the stack [kRegStack or fewer][kThreads] of double4, then
+    // the tile's tip codes [n][kPats]
+    extern __shared__ double4 stack_lds[];
+    uint8_t *tip_lds = reinterpret_cast<uint8_t *>(stack_lds + (size_t)a.reg_depth * RS::kThreads);
+    __shared__ double cat_l[RS::kWaves][64];
+    __shared__ int cat_c[RS::kWaves][64];
+    __shared__ double grp_sum[RS::kGroups];
+    const int tile = blockIdx.x;
+    const TreeDev td = a.trees[a.tile_tree[tile]];
+    const AlnDev *aln = a.alns + td.aln;
+    const int P = aln->P, n = aln->n_taxa, K = aln->K;
+    // the wave index is wave-uniform, so the matrix addresses below are too
+    // and their entries arrive by scalar loads
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int k = wave % KP, grp = wave / KP;
+    const int p0 = (tile - td.tile_begin) * RS::kPats;
+    // tips of the tile into LDS (a pattern past the end reads as all states)
+    for (int x = threadIdx.x; x < n * RS::kPats; x += RS::kThreads) {
+        const int tx = x / RS::kPats, q = p0 + x % RS::kPats;
+        tip_lds[x] = q < P ? ldg(aln->tips + (size_t)tx * P + q) : (uint8_t)15;
+    }
+    __syncthreads();
+    const uint8_t *tips = tip_lds + grp * 64 + lane;
+    // this wave's category of every edge: P(r_k t_e) at pm + e * KP * 16
+    const __attribute__((address_space(4))) double *pm =
+        (const __attribute__((address_space(4))) double *)(a.pmat + td.pm_off) + k * 16;
+    // the 4x4 identity, the matrix of an OP_REVAL's side a (1 x and 0 x are
+    // exact, so I . x = x bit for bit): the plan keeps one after the last
+    // tree's matrices
+    const __attribute__((address_space(4))) double *ident =
+        (const __attribute__((address_space(4))) double *)a.ident;
+    const double thr = ldexp(1.0, -256), up = ldexp(1.0, 256);
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    double4 *stk = stack_lds + threadIdx.x;
+    int cnt = 0;
+    double L = 0.0;
+    // One step of the program.  The compiler emits three side forms (see
+    // compile_loglik_reg): two tips; the accumulator and a tip; a stack slot
+    // and the accumulator.  Each form has its own straight-line code so that
+    // the step's scalar matrix loads and LDS reads all issue before the one
+    // wait for them.
+    // (an OP_REVAL's side a takes the identity matrix: ea < 0, see below)
+    auto step = [&](const Op &op, const double xa[4], const double xb[4], const double *ma, const double *mb,
+                    bool upd) {
+        double y[4], mx = 0.0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const double ya = ma[i * 4] * xa[0] + ma[i * 4 + 1] * xa[1] + ma[i * 4 + 2] * xa[2] +
+                              ma[i * 4 + 3] * xa[3];
+            const double yb = mb[i * 4] * xb[0] + mb[i * 4 + 1] * xb[1] + mb[i * 4 + 2] * xb[2] +
+                              mb[i * 4 + 3] * xb[3];
+            y[i] = ya * yb;
+            mx = fmax(mx, y[i]);
+        }
+        if (!upd) {
+            L = aln->freqs[0] * y[0] + aln->freqs[1] * y[1] + aln->freqs[2] * y[2] + aln->freqs[3] * y[3];
+            return;
+        }
+        const bool scale = mx < thr && mx > 0.0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[i] = scale ? y[i] * up : y[i];
+        cnt += scale ? 1 : 0;
+    };
+    // each op is loaded one step ahead, so its scalar load's round trip
+    // overlaps the previous step
+    Op nx = a.ops[td.op_first];
+    for (int o = 0; o < td.n_first; ++o) {
+        const Op op = nx;
+        if (o + 1 < td.n_first) nx = a.ops[td.op_first + o + 1];
+        if (op.code == OP_RPUSH) {
+            stk[(size_t)op.dst * RS::kThreads] = make_double4(acc[0], acc[1], acc[2], acc[3]);
+            continue;
+        }
+        // both matrices are used on every path, so their loads issue together
+        const bool upd = op.code == OP_RUPDATE;
+        const auto Pa = op.ea >= 0 ? pm + (size_t)op.ea * KP * 16 : ident;
+        const auto Pb = pm + (size_t)op.eb * KP * 16;
+        double ma[16], mb[16], xa[4], xb[4];
+        if (op.a >= 0) {  // two tips
+            const unsigned ca = tips[op.a * RS::kPats], cb = tips[op.b * RS::kPats];
+#pragma unroll
+            for (int x = 0; x < 16; ++x) {
+                ma[x] = Pa[x];
+                mb[x] = Pb[x];
+            }
+            tip_vec(ca, xa);
+            tip_vec(cb, xb);
+            step(op, xa, xb, ma, mb, upd);
+        } else if (op.a == REF_ACC) {  // the accumulator and a tip
+            const unsigned cb = tips[op.b * RS::kPats];
+#pragma unroll
+            for (int x = 0; x < 16; ++x) {
+                ma[x] = Pa[x];
+                mb[x] = Pb[x];
+            }
+            reg_copy(xa, acc);
+            tip_vec(cb, xb);
+            step(op, xa, xb, ma, mb, upd);
+        } else {  // a stack slot and the accumulator
+            const double4 v = stk[(size_t)(REF_STACK0 - op.a) * RS::kThreads];
+#pragma unroll
+            for (int x = 0; x < 16; ++x) {
+                ma[x] = Pa[x];
+                mb[x] = Pb[x];
+            }
+            xa[0] = v.x; xa[1] = v.y; xa[2] = v.z; xa[3] = v.w;
+            reg_copy(xb, acc);
+            step(op, xa, xb, ma, mb, upd);
+        }
+    }
+    // the categories of each pattern meet in LDS
+    cat_l[wave][lane] = L;
+    cat_c[wave][lane] = cnt;
+    __syncthreads();
+    if (k == 0) {
+        const int p = p0 + grp * 64 + lane;
+        double term = 0.0;
+        if (p < P) {
+            int cmin = cat_c[wave][lane];
+            for (int c = 1; c < K; ++c) cmin = min(cmin, cat_c[wave + c][lane]);
+            double s = 0.0;
+            for (int c = 0; c < K; ++c) s += ldexp(cat_l[wave + c][lane], -256 * (cat_c[wave + c][lane] - cmin));
+            term = ldg(aln->w + p) * (log(s) - log((double)K) - (double)cmin * 256.0 * kLn2);
+        }
+        term = wave_sum(term);
+        if (lane == 0) grp_sum[grp] = term;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int g = 0; g < RS::kGroups; ++g) s += grp_sum[g];
+        a.part[(size_t)tile * a.part_cols * 3] = s;
+    }
+}
+
 // Log density of independent Exponential(rate) priors on the E lengths in
 // LDS, sum_e (log rate - rate t_e); 0 for rate 0.  Every thread reads all
 // lengths in the same order, so all hold the same value.
@@ -1216,13 +1434,17 @@ __global__ void __launch_bounds__(BS) k_optimize(const BatchArgs a, double *brle
         const TreeDev td = a.trees[b];
         const AlnDev *aln = a.alns + td.aln;
         const int E = td.n_edges;
-        double *pm = lds;
-        double *tl = lds + (size_t)E * KP * 16;
-        // FP32 partials: an FP32 copy of the matrices for the loop's updates,
-        // 16-byte aligned after the lengths
+        // FP64 partials: the matrices, then the lengths, in LDS.  FP32
+        // partials: the lengths, then (16-byte aligned) an FP32 copy of the
+        // matrices for the loop's updates in LDS, while the FP64 matrices,
+        // read only by the final FP64 evaluation, go to this tree's slice of
+        // the global matrix buffer (so a 64-taxon tree's table still fits
+        // in LDS beside them).
         constexpr bool kF32 = std::is_same<T, float>::value;
         constexpr bool kFuseUpd = GRP && TAB_LDS && FuseFirst<KP>::value && BS == 256;
-        float *pmf = reinterpret_cast<float *>(lds + (((size_t)E * KP * 16 + E + 1) & ~(size_t)1));
+        double *pm = kF32 ? a.pmat + td.pm_off : lds;
+        double *tl = kF32 ? lds : lds + (size_t)E * KP * 16;
+        float *pmf = reinterpret_cast<float *>(lds + (((size_t)E + 1) & ~(size_t)1));
         for (int e = tid; e < E; e += BS) tl[e] = fmin(fmax(brlen[td.edge_off + e], opt.t_min), opt.t_max);
         model_to_lds(aln, &model);
         if (GRP && tid == 0) {
@@ -1231,15 +1453,15 @@ __global__ void __launch_bounds__(BS) k_optimize(const BatchArgs a, double *brle
             gsh.g = g;
             gsh.seq = 0;
             gsh.is_broken = 0;
-            gsh.arrive = base;
-            gsh.broken = base + 1;
-            gsh.slots = base + 2;
+            gsh.broken = base;
+            gsh.slots = base + 1;
         }
         __syncthreads();
         for (int x = tid; x < E * KP * 16; x += BS) {
             const int e = x / (KP * 16), r = x % (KP * 16);
-            pm[x] = pm_entry(&model, r >> 4, r & 15, tl[e]);
-            if (kF32) pmf[x] = (float)pm[x];
+            const double pe = pm_entry(&model, r >> 4, r & 15, tl[e]);
+            pm[x] = pe;
+            if (kF32) pmf[x] = (float)pe;
         }
         __syncthreads();
         TreeView<T> v = make_view<T>(td, aln, a, &model, pm);
@@ -1310,7 +1532,19 @@ __global__ void __launch_bounds__(BS) k_optimize(const BatchArgs a, double *brle
                 pc[PROF_NEWTON_ITERS] += r.iters;
                 pc[PROF_CYC_TABLE] += r.cyc_table;
                 pc[PROF_CYC_ITERS] += r.cyc_iters;
-                max_rel = fmax(max_rel, fabs(r.t - t0) / fmax(t0, 1e-6));
+                // A step counts against convergence when it moves the length
+                // by more than tol_t relative, unless it starts or ends at a
+                // bound and its gain by the quadratic model at the start is
+                // negligible (below tol_lnl / E; the bound is then optimal to
+                // within that gain).  With FP32 partials a length whose
+                // optimum lies at t_min otherwise never settles: the
+                // derivative there is at the noise level, and Newton keeps
+                // moving the length on and off the bound by amounts tiny in
+                // absolute terms but large relative to the 1e-6 floor of the
+                // relative change, for no gain.
+                const bool at_bound = t0 <= opt.t_min || t0 >= opt.t_max || r.t <= opt.t_min || r.t >= opt.t_max;
+                if (!(at_bound && r.gain < opt.tol_lnl / E))
+                    max_rel = fmax(max_rel, fabs(r.t - t0) / fmax(t0, 1e-6));
                 if (r.t != t0) {
                     if (tid == 0) tl[e] = r.t;
                     if constexpr (KP * 16 <= 64) {
@@ -1374,7 +1608,7 @@ __global__ void __launch_bounds__(BS) k_optimize(const BatchArgs a, double *brle
             for (int o = 0; o < td.n_final; ++o) {
                 const Op op = a.ops[td.op_final + o];
                 if (op.code == OP_UPDATE) {
-                    do_update<double, BS, KP>(vd, op, 0, ni);
+                    do_update<double, BS, KP, kPmGlobal>(vd, op, 0, ni);
                 } else {
                     const Sums3 r =
                         eval_edge<double, BS, KP>(vd, op.a, op.b, 0, ni, tl[op.dst], red, wx, parity, gs);
@@ -1516,6 +1750,30 @@ hipError_t launch_tiles(int precision, int kp, const BatchArgs &a, const double 
     if (a.n_tiles <= 0) return hipSuccess;
     PT_KP_SWITCH(return precision == PT_FP32 ? launch_tiles_t<float, kTileBlock, KP>(a, brlen, lds, s)
                                              : launch_tiles_t<double, kTileBlock, KP>(a, brlen, lds, s));
+    return hipErrorInvalidValue;
+}
+
+int loglik_reg_tile_patterns(int kp) {
+    PT_KP_SWITCH(return RegShape<KP>::kPats);
+    return 0;
+}
+
+size_t loglik_reg_lds(int kp, int n, int depth) {
+    PT_KP_SWITCH(return (size_t)depth * RegShape<KP>::kThreads * sizeof(double4) + (size_t)n * RegShape<KP>::kPats);
+    return 0;
+}
+
+hipError_t launch_loglik_reg(int kp, const BatchArgs &a, size_t lds_bytes, hipStream_t s) {
+    if (a.n_tiles <= 0) return hipSuccess;
+    PT_KP_SWITCH({
+        if (lds_bytes > 48 * 1024) {
+            hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_loglik_reg<KP>),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+            if (e != hipSuccess) return e;
+        }
+        hipLaunchKernelGGL((k_loglik_reg<KP>), dim3(a.n_tiles), dim3(RegShape<KP>::kThreads), lds_bytes, s, a);
+        return hipGetLastError();
+    });
     return hipErrorInvalidValue;
 }
 

@@ -28,6 +28,8 @@ struct BatchArgs {
     long long *prof;            // optimisation: per-tree phase counters [n_trees][8], or null
     int32_t groups;             // optimisation: blocks per tree (1: one block per tree, work queue)
     unsigned long long *gsync;  // optimisation with groups > 1: per-tree cross-block words, zeroed
+    int32_t reg_depth;          // register-resident lnL: stack slots of the deepest tree
+    const double *ident;        // register-resident lnL: the 4x4 identity (16 doubles)
 };
 
 // Optimisation with several blocks per tree: at most kGroupBlocksMax blocks,
@@ -61,6 +63,13 @@ hipError_t launch_pmat(const BatchArgs &a, const double *brlen, hipStream_t s);
 // lds_bytes: the largest tree's transition matrices (used with FP64 partials).
 hipError_t launch_tiles(int precision, int kp, const BatchArgs &a, const double *brlen, size_t lds_bytes,
                         hipStream_t s);
+// Register-resident lnL (k_loglik_reg): patterns per tile for a padded
+// category count, its LDS for n taxa and a stack of `depth` slots, and the
+// launch (one block per tile; a.tile_tree, a.part, a.n_tiles and
+// a.reg_depth describe the register tiles; lds_bytes from loglik_reg_lds).
+int loglik_reg_tile_patterns(int kp);
+size_t loglik_reg_lds(int kp, int n, int depth);
+hipError_t launch_loglik_reg(int kp, const BatchArgs &a, size_t lds_bytes, hipStream_t s);
 hipError_t launch_reduce(bool grad, const BatchArgs &a, double *lnl, double *grad_out,
                          double *hess_out, hipStream_t s);
 // With a.groups > 1, grid = trees x groups and a.gsync zeroed beforehand.

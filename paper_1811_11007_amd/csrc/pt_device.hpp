@@ -22,7 +22,17 @@ enum : int32_t {
     OP_UPDATE = 1,  // dst = (P(ea) . side a) * (P(eb) . side b), then scaling
     OP_NEWTON = 2,  // optimise the length of edge e between sides a and b
     OP_EVAL = 3,    // lnL (and derivatives) across edge e; out = output column
+    // Register programs (the lnL with every partial kept in registers):
+    OP_RUPDATE = 4,  // acc = (P(ea) . side a) * (P(eb) . side b), then scaling
+    OP_RPUSH = 5,    // stack slot dst = acc
+    OP_REVAL = 6,    // lnL across edge eb: pi . (side a * (P(eb) . side b)); ea = -1
 };
+
+// Side references of register programs: a leaf's tip (>= 0), the
+// accumulator, or stack slot REF_STACK0 - ref.
+constexpr int32_t REF_ACC = -1;
+constexpr int32_t REF_STACK0 = -2;
+constexpr int kRegStack = 8;  // stack slots of the register kernel
 
 struct Op {
     int32_t code;

@@ -34,6 +34,9 @@ void compile_loglik(const Tree &t, std::vector<Op> &ops);
 // in two thirds of a tree's partial buffer at twice the element size (the
 // FP64 evaluation that ends an FP32 optimisation reuses the FP32 buffer).
 void compile_loglik_dense(const Tree &t, std::vector<Op> &ops);
+// lnL as a register program (OP_RUPDATE / OP_RPUSH / OP_REVAL, rooted on
+// edge 0); returns the stack slots it needs.
+int compile_loglik_reg(const Tree &t, std::vector<Op> &ops);
 // Every directional partial once, then EVAL on every edge (column = edge).
 void compile_grad(const Tree &t, std::vector<Op> &ops);
 // Smoothing passes over the masked edges in depth-first edge order: before

@@ -171,6 +171,76 @@ void compile_loglik_dense(const Tree &t, std::vector<Op> &ops) {
     }
 }
 
+// Register program of the lnL: Felsenstein's post-order pass rooted on edge
+// 0, written for a machine whose only partials are an accumulator and a
+// small stack.  Of an internal node's two child subtrees, the one needing
+// more stack is evaluated first (Sethi and Ullman 1970), so a tree of n taxa
+// needs at most floor(log2 n) - 1 stack slots.  Side references: >= 0 a
+// leaf's tip, REF_ACC the accumulator, <= REF_STACK0 stack slot
+// REF_STACK0 - ref.  Every OP_RUPDATE and OP_REVAL has one of three side
+// forms, (tip, tip), (accumulator, tip) or (stack slot, accumulator), which
+// the kernel relies on.
+int compile_loglik_reg(const Tree &t, std::vector<Op> &ops) {
+    const int n = t.n;
+    auto child_pair = [&](int v, int parent, int c[2], int e[2]) {
+        int k = 0;
+        for (int j = 0; j < 3; ++j)
+            if (t.nbr[3 * v + j] != parent) { c[k] = t.nbr[3 * v + j]; e[k] = t.nedge[3 * v + j]; ++k; }
+    };
+    std::function<int(int, int)> need = [&](int v, int parent) -> int {
+        if (v < n) return 0;
+        int c[2], e[2];
+        child_pair(v, parent, c, e);
+        const int a = need(c[0], v), b = need(c[1], v);
+        return a == b ? a + 1 : std::max(a, b);
+    };
+    int depth = 0;
+    auto emit_op = [&](int code, int dst, int a, int ea, int b, int eb) {
+        Op op{};
+        op.code = code;
+        op.dst = dst;
+        op.a = a;
+        op.ea = ea;
+        op.b = b;
+        op.eb = eb;
+        ops.push_back(op);
+    };
+    // Leaves the partial of v's side (seen from parent) in the accumulator,
+    // using stack slots from sp up.
+    std::function<void(int, int, int)> emit = [&](int v, int parent, int sp) {
+        int c[2], e[2];
+        child_pair(v, parent, c, e);
+        if (need(c[1], v) > need(c[0], v)) { std::swap(c[0], c[1]); std::swap(e[0], e[1]); }
+        if (c[0] < n) {  // two tips
+            emit_op(OP_RUPDATE, 0, c[0], e[0], c[1], e[1]);
+        } else if (c[1] < n) {
+            emit(c[0], v, sp);
+            emit_op(OP_RUPDATE, 0, REF_ACC, e[0], c[1], e[1]);
+        } else {
+            emit(c[0], v, sp);
+            emit_op(OP_RPUSH, sp, 0, 0, 0, 0);
+            depth = std::max(depth, sp + 1);
+            emit(c[1], v, sp + 1);
+            emit_op(OP_RUPDATE, 0, REF_STACK0 - sp, e[0], REF_ACC, e[1]);
+        }
+    };
+    int u = t.ends[0], v = t.ends[1];
+    if (need(v, u) > need(u, v)) std::swap(u, v);  // u's side first
+    if (u < n) {  // two tips (n = 2)
+        emit_op(OP_REVAL, 0, u, -1, v, 0);
+    } else if (v < n) {
+        emit(u, v, 0);
+        emit_op(OP_REVAL, 0, REF_ACC, -1, v, 0);
+    } else {
+        emit(u, v, 0);
+        emit_op(OP_RPUSH, 0, 0, 0, 0, 0);
+        depth = std::max(depth, 1);
+        emit(v, u, 1);
+        emit_op(OP_REVAL, 0, REF_STACK0, -1, REF_ACC, 0);
+    }
+    return depth;
+}
+
 void compile_grad(const Tree &t, std::vector<Op> &ops) {
     Slots s(t);
     s.out = &ops;

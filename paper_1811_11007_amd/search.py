@@ -47,7 +47,8 @@ class SearchResult:
     full_time_s: float
     proposal_time_s: float
     batches: int
-    warm_better: int = 0  # proposals whose warm-started partial optimum beat the cold-started one
+    cold_redo: int = 0    # warm-started proposals near the gate optimised again from the cold start
+    cold_better: int = 0  # of those, the ones whose cold-started partial optimum was better
     samples: list = field(default_factory=list)  # (features, parent lengths, optimised lengths) of the
                                                  # five touched edges, when collecting
 
@@ -72,13 +73,14 @@ class WarmStart:
 
 class ThresholdSearch:
     def __init__(self, ctx, aln, threshold=-10.0, radius=0, warm: WarmStart | None = None,
-                 precision=L.PT_FP32, batch=1024, opt=None):
+                 precision=L.PT_FP32, batch=1024, opt=None, warm_margin=20.0):
         if threshold >= 0:
             raise ValueError("the threshold offset T must be negative")
         if int(radius) != radius or radius < -1:
             raise ValueError("radius must be an integer >= 0, or -1 for all edges")
         self.ctx, self.aln, self.T, self.radius, self.warm = ctx, aln, float(threshold), int(radius), warm
         self.precision, self.batch = precision, int(batch)
+        self.warm_margin = float(warm_margin)
         self.opt = opt if opt is not None else L.opt_default(precision)
         self.n = aln.n_taxa
 
@@ -109,6 +111,44 @@ class ThresholdSearch:
         plan.close()
         return out
 
+    def _propose(self, chunk, radius, gate, stats):
+        """Partial optimisation of one chunk of proposals; returns (lnL per
+        proposal, lengths concatenated).  With a warm start each proposal
+        starts from the network's lengths; those whose warm lnL falls short
+        of the gate by at most warm_margin are optimised again from the
+        cold start (the parent's lengths) and keep the better result, so
+        the network decides alone only where the cold start is far from the
+        gate."""
+        n = self.n
+        E = 2 * n - 3
+        nc = len(chunk)
+        trees = [p[1] for p in chunk]
+        starts = np.concatenate([p[2] for p in chunk])
+        masks = None
+        if radius >= 0:
+            masks = list(L.pt_radius_masks(n, np.stack(trees), [p[4][0] for p in chunk], radius))
+        t0 = time.perf_counter()
+        if self.warm is None:
+            lnl, bo, _ = self._optimize(trees, starts, masks)
+            stats["prop_time"] += time.perf_counter() - t0
+            return lnl, bo
+        X = np.stack([p[3] for p in chunk]).astype(np.float32)
+        pos = np.stack([i * E + p[4] for i, p in enumerate(chunk)]).astype(np.int32)
+        base = np.stack([p[5][p[4]] for p in chunk])
+        lnl, bo, _ = self._optimize(trees, starts, masks, (X, pos, base))
+        redo = [i for i in range(nc) if gate - self.warm_margin <= lnl[i] < gate]
+        stats["cold_redo"] = stats.get("cold_redo", 0) + len(redo)
+        if redo:
+            lc, bc, _ = self._optimize([trees[i] for i in redo], np.concatenate([chunk[i][2] for i in redo]),
+                                       None if masks is None else [masks[i] for i in redo])
+            for j, i in enumerate(redo):
+                if lc[j] > lnl[i]:
+                    lnl[i] = lc[j]
+                    bo[i * E:(i + 1) * E] = bc[j * E:(j + 1) * E]
+                    stats["cold_better"] = stats.get("cold_better", 0) + 1
+        stats["prop_time"] += time.perf_counter() - t0
+        return lnl, bo
+
     def run(self, starts, collect=False, max_samples=None, progress=None):
         """starts: list of (edges, brlen).  With collect, every proposal is
         fully optimised and (features, parent and optimised lengths of the
@@ -127,7 +167,7 @@ class ThresholdSearch:
         good = {}
         lmax = -np.inf
         stats = dict(proposed=0, queued=len(todo), full_passes=0, full_time=0.0, prop_time=0.0, batches=0,
-                     warm_better=0)
+                     cold_redo=0, cold_better=0)
         samples = []
         n_samples = 0
         head = 0
@@ -155,7 +195,12 @@ class ThresholdSearch:
                     bi = bo[i * E:(i + 1) * E].copy()
                     good[k] = (float(lnl[i]), e, bi)
                     parents.append((e, bi))
-            # ---- propose the unvisited neighbours of the good ones
+            # ---- propose the unvisited neighbours of the good ones.  A key
+            # joins the queue only when one of its proposals passes the gate,
+            # so a neighbour rejected from one parent's lengths is proposed
+            # again by a later good parent (the paper proposes every
+            # unvisited neighbour); a key proposed by several parents in one
+            # round is optimised once per parent and keeps the best.
             props = []  # (key, edges, start brlen, features row, touched, parent brlen)
             for e, b in parents:
                 ne, nb, tt = L.pt_nni_neighbors(n, e, b)
@@ -165,61 +210,39 @@ class ThresholdSearch:
                     k = ks[j].tobytes()
                     if k in visited or k in queued:
                         continue
-                    queued.add(k)
                     props.append((k, ne[j], nb[j], None if F is None else F[j], tt[j], b))
             stats["proposed"] += len(props)
             if progress is not None:
                 progress("batch %d: %d visited, %d good, %d new proposals, lmax %.4f" % (
                     stats["batches"], len(visited), len(good), len(props), lmax))
             radius = -1 if collect else self.radius
-            # with a warm start every proposal is optimised from both starts in
-            # the same launch and keeps the better result: the cold start stays
-            # the fallback, so the gate is never looser than without the network
-            dual = self.warm is not None
-            step = max(1, self.batch // 2) if dual else self.batch
-            for s in range(0, len(props), step):
+            gate = lmax + self.T
+            best = {}  # key -> (partial lnL, edges, lengths)
+            for s0 in range(0, len(props), self.batch):
                 if max_samples is not None and n_samples >= max_samples:
                     break
-                chunk = props[s:s + step]
-                nc = len(chunk)
-                trees = [p[1] for p in chunk]
-                starts = np.concatenate([p[2] for p in chunk])
-                masks = None
-                if radius >= 0:
-                    masks = list(L.pt_radius_masks(n, np.stack(trees), [p[4][0] for p in chunk], radius))
-                warm_rows = None
-                if dual:
-                    X = np.stack([p[3] for p in chunk]).astype(np.float32)
-                    pos = np.stack([(nc + i) * E + p[4] for i, p in enumerate(chunk)]).astype(np.int32)
-                    base = np.stack([p[5][p[4]] for p in chunk])
-                    warm_rows = (X, pos, base)
-                    trees = trees + trees
-                    starts = np.concatenate([starts, starts])
-                    masks = None if masks is None else masks + masks
-                t0 = time.perf_counter()
-                lnl, bo, ps = self._optimize(trees, starts, masks, warm_rows)
-                stats["prop_time"] += time.perf_counter() - t0
+                chunk = props[s0:s0 + self.batch]
+                lnl, bo = self._propose(chunk, radius, gate, stats)
                 for i, p in enumerate(chunk):
-                    j = i
-                    if dual and lnl[nc + i] > lnl[i]:
-                        j = nc + i
-                        stats["warm_better"] += 1
-                    li = lnl[j]
-                    bi = bo[j * E:(j + 1) * E].copy()
+                    bi = bo[i * E:(i + 1) * E]
                     if collect:
                         tt = p[4]
                         samples.append((p[3], p[5][tt].copy(), bi[tt].copy()))
                         n_samples += 1
-                    if li >= lmax + self.T:
-                        todo.append((p[0], p[1], bi))
-                        stats["queued"] += 1
+                    if lnl[i] >= gate and (p[0] not in best or lnl[i] > best[p[0]][0]):
+                        best[p[0]] = (lnl[i], p[1], bi.copy())
+            for k, (_, e, bi) in best.items():
+                queued.add(k)
+                todo.append((k, e, bi))
+                stats["queued"] += 1
             if max_samples is not None and n_samples >= max_samples:
                 break
         final = {k: v for k, v in good.items() if v[0] >= lmax + self.T}
         return SearchResult(lmax=lmax, good=final, visited=len(visited), proposed=stats["proposed"],
                             queued=stats["queued"], full_passes=stats["full_passes"],
                             full_time_s=stats["full_time"], proposal_time_s=stats["prop_time"],
-                            batches=stats["batches"], warm_better=stats["warm_better"], samples=samples)
+                            batches=stats["batches"], cold_redo=stats["cold_redo"],
+                            cold_better=stats["cold_better"], samples=samples)
 
 
 def hls_summary(n, result):

@@ -1,0 +1,215 @@
+"""GPU parity at the benchmark shapes, element by element against stored
+oracle results (written by tests/golden/make_c3.py and make_c4.py, which
+call only the oracle) and against the oracle run live.
+
+* Batching: all 512 topologies over four uneven alignments (27x1949,
+  36x1812, 50x1133, 64x1008), optimised in one persistent launch in the
+  shape the benchmark times (autotuned, replayed from a HIP graph), FP32 and
+  FP64; every optimum against the oracle's local maxima of that topology;
+  the likelihood at the starting lengths against the oracle's.
+* Differentiation: lnL and all 97 branch-length derivatives of 256 trees of
+  50 taxa x 1500 sites, FP32 and FP64, against the oracle gradient; the
+  FP64 gradient against central differences of the oracle lnL on 8 trees.
+* Search shape: lnL of 32 trees of 64 taxa x 2500 sites (1711 patterns),
+  both precisions, against the oracle.
+
+Tolerances (the method's parity bars): FP64 within 1e-6 relative (checked
+tighter where the arithmetic allows); FP32 partials within 1e-4 absolute
+in lnL; FP32 gradients within 1e-3 * max(1, |g|).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import paper_1811_11007_amd as pt
+from oracle import core as oc
+from synth import workloads
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+FP64_REL = 1e-6
+FP32_ABS = 1e-4
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = pt.Context(0)
+    yield c
+    c.close()
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def c3():
+    alns, trees, lens, idx = workloads.c3_inputs()
+    g = json.load(open(os.path.join(GOLDEN, "c3_batch512.json")))
+    for a, s in zip(alns, g["alignments"]):
+        assert a.n_patterns == s["n_patterns"] and int(a.tips.astype(np.int64).sum()) == s["tips_sum"], \
+            "generator output differs from the stored workload"
+    assert abs(float(np.sum(lens)) - g["lens_sum"]) < 1e-9
+    return alns, trees, lens, idx, g
+
+
+def test_c3_loglik_all_512(ctx, c3):
+    """lnL of the 512 topologies at their starting lengths, one plan over
+    four alignments, both precisions."""
+    alns, trees, lens, idx, g = c3
+    want = np.asarray(g["start_lnl"])
+    A = [pt.Alignment.from_synth(ctx, a) for a in alns]
+    T = pt.Trees(trees, idx)
+    got64 = pt.pt_batch_loglik(ctx, A, T, lens, pt.PT_FP64)
+    got32 = pt.pt_batch_loglik(ctx, A, T, lens, pt.PT_FP32)
+    r64 = np.max(np.abs(got64 - want) / np.abs(want))
+    a32 = np.max(np.abs(got32 - want))
+    say("C3 start lnL: fp64 max rel", r64, "fp32 max abs", a32)
+    assert r64 < 1e-11
+    assert a32 < FP32_ABS
+
+
+def test_c3_batched_optimisation_all_512(ctx, c3):
+    """All 512 optima against the oracle's, in the benchmark's launch
+    configuration (one persistent launch, autotuned shape, HIP graph)."""
+    import torch
+    alns, trees, lens, idx, g = c3
+    want = np.asarray(g["opt_lnl"])
+    start = np.asarray(g["start_lnl"])
+    A = [pt.Alignment.from_synth(ctx, a) for a in alns]
+    T = pt.Trees(trees, idx)
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream()
+    res = {}
+    for prec in (pt.PT_FP32, pt.PT_FP64):
+        plan = pt.Plan(ctx, A, T, pt.PT_PLAN_OPTIMIZE, prec)
+        b0 = torch.tensor(lens, dtype=torch.float64, device=dev)
+        b = torch.empty_like(b0)
+        lnl = torch.zeros(T.n_trees, dtype=torch.float64, device=dev)
+        st = torch.zeros(T.n_trees, dtype=torch.int32, device=dev)
+        ps = torch.zeros(T.n_trees, dtype=torch.int32, device=dev)
+        with torch.cuda.stream(stream):
+            plan.autotune(b0)
+            plan.set_graphs(True)
+            for _ in range(2):  # the second call replays the captured graph
+                b.copy_(b0, non_blocking=True)
+                plan.optimize(b, lnl, ps, st, stream=stream)
+            stream.synchronize()
+        res[prec] = (lnl.cpu().numpy(), b.cpu().numpy(), st.cpu().numpy(), ps.cpu().numpy())
+        say("C3", "fp32" if prec == pt.PT_FP32 else "fp64", "shape", plan.launch_shape(),
+            "passes mean %.2f max %d" % (res[prec][3].mean(), res[prec][3].max()))
+        plan.close()
+    l32, b32, s32, _ = res[pt.PT_FP32]
+    l64, b64, s64, _ = res[pt.PT_FP64]
+    assert np.all(s32 == 0) and np.all(s64 == 0)
+    assert np.all(l64 >= start - 1e-6 * np.abs(start))
+    # Every optimum must be one of the oracle's local maxima of that topology
+    # (several exist on some topologies; which one an ascent reaches depends
+    # on its path): the one the oracle reaches from the same start, or one it
+    # reaches from its two further starts.
+    optima = g["local_optima"]
+    r64 = np.array([min(abs(l64[i] - x) / abs(x) for x in optima[i]) for i in range(len(optima))])
+    a32 = np.array([min(abs(l32[i] - x) for x in optima[i]) for i in range(len(optima))])
+    same64 = np.abs(l64 - want) / np.abs(want) < FP64_REL
+    same32 = np.abs(l32 - want) < FP32_ABS
+    say("C3 optima vs oracle: fp64 max rel", r64.max(), "fp32 max abs", a32.max(),
+        "worst fp32 topology", int(np.argmax(a32)))
+    say("C3 topologies at the oracle's same-start optimum: fp64 %d, fp32 %d of %d; elsewhere (fp64):"
+        % (same64.sum(), same32.sum(), len(want)),
+        [(i, round(float(l64[i] - want[i]), 4)) for i in np.nonzero(~same64)[0]])
+    assert r64.max() < FP64_REL
+    assert a32.max() < FP32_ABS
+    # the reported lnL is the lnL at the reported lengths
+    at = pt.pt_batch_loglik(ctx, A, T, b64, pt.PT_FP64)
+    assert np.max(np.abs(at - l64) / np.abs(l64)) < 1e-12
+    at32 = pt.pt_batch_loglik(ctx, A, T, b32, pt.PT_FP64)
+    assert np.max(np.abs(at32 - l32)) < 1e-9 * np.max(np.abs(l32))
+
+
+@pytest.fixture(scope="module")
+def c4():
+    aln, tops, lens = workloads.c4_inputs()
+    g = json.load(open(os.path.join(GOLDEN, "c4_grad256.json")))
+    assert aln.n_patterns == g["n_patterns"] and int(aln.tips.astype(np.int64).sum()) == g["tips_sum"], \
+        "generator output differs from the stored workload"
+    assert abs(float(np.sum(lens)) - g["lens_sum"]) < 1e-9
+    return aln, tops, lens, g
+
+
+def test_c4_gradients_all_256(ctx, c4):
+    """lnL and every branch-length derivative of the 256 trees, FP32 and
+    FP64, against the oracle gradient."""
+    aln, tops, lens, g = c4
+    wl = np.asarray(g["lnl"])
+    wg = np.asarray(g["grad"])
+    A = pt.Alignment.from_synth(ctx, aln)
+    T = pt.Trees(tops)
+    l64, g64, _ = pt.pt_batch_branch_grad(ctx, [A], T, lens.ravel(), pt.PT_FP64)
+    l32, g32, _ = pt.pt_batch_branch_grad(ctx, [A], T, lens.ravel(), pt.PT_FP32)
+    g64 = g64.reshape(256, 97)
+    g32 = g32.reshape(256, 97)
+    scale = np.maximum(1.0, np.abs(wg))
+    e64 = np.max(np.abs(g64 - wg) / scale)
+    e32 = np.max(np.abs(g32 - wg) / scale)
+    say("C4 fp64: lnL max rel", np.max(np.abs(l64 - wl) / np.abs(wl)), "grad max err", e64)
+    say("C4 fp32: lnL max abs", np.max(np.abs(l32 - wl)), "grad max err", e32)
+    assert np.max(np.abs(l64 - wl) / np.abs(wl)) < 1e-11
+    assert e64 < 1e-7
+    assert np.max(np.abs(l32 - wl)) < FP32_ABS
+    assert e32 < 1e-3
+
+
+def test_c4_gradient_finite_differences(ctx, c4):
+    """FP64 gradient of 8 trees against central differences of the oracle
+    lnL (step h = min(1e-5, t/4), so that t - h stays positive on the
+    shortest branches, with one Richardson extrapolation over steps h and
+    h/2: plain central differences at h = 1e-5 carry up to 2.5e-3 of
+    truncation error on branches of a few 1e-5); the hessian diagonal
+    against the oracle's."""
+    aln, tops, lens, _ = c4
+    pick = [0, 37, 74, 111, 148, 185, 222, 255]
+    A = pt.Alignment.from_synth(ctx, aln)
+    T = pt.Trees([tops[i] for i in pick])
+    _, g, hd = pt.pt_batch_branch_grad(ctx, [A], T, lens[pick].ravel(), pt.PT_FP64, hess=True)
+    g = g.reshape(8, 97)
+    hd = hd.reshape(8, 97)
+    D = oc.Data.from_alignment(aln)
+    worst = 0.0
+
+    def central(i, e, h):
+        bp, bm = lens[i].copy(), lens[i].copy()
+        bp[e] += h
+        bm[e] -= h
+        return (oc.loglik(D, tops[i], bp) - oc.loglik(D, tops[i], bm)) / (2 * h)
+
+    for j, i in enumerate(pick):
+        fd = np.zeros(97)
+        for e in range(97):
+            h = min(1e-5, lens[i][e] / 4)
+            fd[e] = (4 * central(i, e, h / 2) - central(i, e, h)) / 3
+        err = np.max(np.abs(g[j] - fd) / np.maximum(1.0, np.abs(fd)))
+        worst = max(worst, err)
+        _, _, wh = oc.gradient(D, tops[i], lens[i])
+        assert np.max(np.abs(hd[j] - wh) / np.maximum(1.0, np.abs(wh))) < 1e-8
+    say("C4 fp64 gradient vs central differences, 8 trees: max err", worst)
+    assert worst < 1e-4
+
+
+def test_c5_shape_loglik(ctx):
+    """lnL of 32 trees of 64 taxa x 2500 sites (the search workload's
+    alignment, 1711 patterns), both precisions, against the oracle."""
+    aln, tops, lens = workloads.c5_loglik_trees(6, 32)
+    D = oc.Data.from_alignment(aln)
+    want = np.array([oc.loglik(D, t, b) for t, b in zip(tops, lens)])
+    A = pt.Alignment.from_synth(ctx, aln)
+    T = pt.Trees(tops)
+    got64 = pt.pt_batch_loglik(ctx, [A], T, lens.ravel(), pt.PT_FP64)
+    got32 = pt.pt_batch_loglik(ctx, [A], T, lens.ravel(), pt.PT_FP32)
+    r64 = np.max(np.abs(got64 - want) / np.abs(want))
+    a32 = np.max(np.abs(got32 - want))
+    say("C5 shape lnL (%d patterns): fp64 max rel" % aln.n_patterns, r64, "fp32 max abs", a32)
+    assert r64 < 1e-11
+    assert a32 < FP32_ABS

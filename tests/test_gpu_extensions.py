@@ -1,9 +1,10 @@
 """GPU tests of the batching and differentiation extensions and of the ABI's
 plan, graph, mask, arena-cap and error behaviour, against the FP64 oracle.
 
-Workload shapes: 256 trees of 50 taxa x 1500 sites GTR+G4 (gradients),
-512 topologies over four uneven alignments 27x1949, 36x1812, 50x1133,
-64x1008 (batched optimisation), small trees for the edge cases.
+Workload shapes: 256 trees of 50 taxa x 1500 sites GTR+G4 (gradients
+through torch autograd), small trees for the edge cases.  The full
+benchmark shapes (all 512 batched optima, all 256 gradients) are checked in
+test_gpu_configs.py.
 """
 import os
 
@@ -34,12 +35,8 @@ def say(*a):
 def c4_inputs(n_trees=256):
     """50 taxa x 1500 sites GTR+G4; topologies from an NNI walk around the
     generating tree, lengths ~ Exp(mean 0.05)."""
-    rng = np.random.default_rng(4)
-    e, b = synth.yule_tree(50, rng, mean=0.05)
-    aln = synth.make_alignment(e, b, 50, 1500, rng, alpha=0.5, n_cats=4)
-    tops = [x for x, _ in synth.nni_bfs(e, b, 50, n_trees)]
-    lens = rng.exponential(0.05, size=(n_trees, 97))
-    return aln, tops, lens
+    from synth import workloads
+    return workloads.c4_inputs(n_trees)
 
 
 def test_autograd_c4_against_oracle(ctx):
@@ -97,55 +94,6 @@ def test_autograd_gradcheck(ctx):
     x = torch.tensor(rng.exponential(0.1, 39) + 0.01, dtype=torch.float64, device="cuda", requires_grad=True)
     assert torch.autograd.gradcheck(lambda y: PTLogLik.apply(y, plan, edge_tree), (x,), eps=1e-6, atol=1e-4,
                                     rtol=1e-5)
-
-
-def c3_inputs():
-    import bench
-    return bench.c3_inputs()
-
-
-def test_c3_batched_optimisation(ctx):
-    """512 topologies over four uneven alignments in one persistent launch
-    (autotuned, replayed from a HIP graph)."""
-    import torch
-    alns, trees, lens, idx = c3_inputs()
-    A = [pt.Alignment.from_synth(ctx, a) for a in alns]
-    T = pt.Trees(trees, idx)
-    dev = torch.device("cuda:0")
-    stream = torch.cuda.Stream()
-    start = pt.pt_batch_loglik(ctx, A, T, lens, pt.PT_FP64)
-    res = {}
-    for prec in (pt.PT_FP32, pt.PT_FP64):
-        plan = pt.Plan(ctx, A, T, pt.PT_PLAN_OPTIMIZE, prec)
-        b0 = torch.tensor(lens, dtype=torch.float64, device=dev)
-        b = torch.empty_like(b0)
-        lnl = torch.zeros(T.n_trees, dtype=torch.float64, device=dev)
-        st = torch.zeros(T.n_trees, dtype=torch.int32, device=dev)
-        with torch.cuda.stream(stream):
-            plan.autotune(b0)
-            plan.set_graphs(True)
-            b.copy_(b0, non_blocking=True)
-            plan.optimize(b, lnl, d_status=st, stream=stream)
-            stream.synchronize()
-        res[prec] = (lnl.cpu().numpy(), b.cpu().numpy(), st.cpu().numpy())
-        plan.close()
-    l32, b32, s32 = res[pt.PT_FP32]
-    l64, b64, s64 = res[pt.PT_FP64]
-    say("C3 converged", int((s32 == 0).sum()), int((s64 == 0).sum()), "max |fp32-fp64|", np.max(np.abs(l32 - l64)))
-    assert np.all(s32 == 0) and np.all(s64 == 0)
-    assert np.all(l64 >= start - 1e-6)
-    assert np.max(np.abs(l32 - l64)) < FP32_ABS
-    # the reported lnL is the lnL at the reported lengths
-    at = pt.pt_batch_loglik(ctx, A, T, b64, pt.PT_FP64)
-    assert np.max(np.abs(at - l64) / np.abs(l64)) < 1e-12
-    # oracle on one topology of each of the two smaller alignments
-    offs = T.edge_offset
-    for i in (5, 130):
-        D = oc.Data.from_alignment(alns[idx[i]])
-        want = oc.optimize(D, trees[i], lens[offs[i]:offs[i + 1]])[0]
-        say("C3 tree", i, "oracle", want, "fp64", l64[i] - want, "fp32", l32[i] - want)
-        assert abs(l64[i] - want) < 1e-6 * abs(want)
-        assert abs(l32[i] - want) < FP32_ABS
 
 
 def test_graph_replays_match_eager(ctx):

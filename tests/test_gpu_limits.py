@@ -2,8 +2,12 @@
 
 - Branch optimisation accepts up to 32768 patterns per alignment and refuses
   more with PT_EUNSUPPORTED; the likelihood has no such limit.
-- A tree's transition matrices must fit the 64 KiB cache: with four rate
-  categories 64 taxa (125 edges) fit and 65 taxa are refused.
+- Transition matrices held in LDS must fit the device's LDS per block: the
+  paper's largest inputs (67 taxa, Methods, "Data and Run-time
+  Parameters") with four rate categories are evaluated, optimised and
+  differentiated in both precisions; a tree far beyond any LDS (150 taxa,
+  eight categories: about 300 KB of FP64 matrices) is refused for
+  optimisation, while its lnL either matches the oracle or is refused.
 """
 import numpy as np
 import pytest
@@ -63,17 +67,71 @@ def test_pattern_limit_of_optimisation(ctx, P):
     assert abs(lo[0] - wo) <= 1e-6 * abs(wo)
 
 
-def test_edge_category_limit(ctx):
-    rng = np.random.default_rng(91)
-    for n, ok in ((64, True), (65, False)):
-        e, b = synth.yule_tree(n, rng, mean=0.05)
-        aln = synth.make_alignment(e, b, n, 200, rng, alpha=0.5, n_cats=4)
-        A = pt.Alignment.from_synth(ctx, aln)
-        if ok:
-            l = pt.pt_batch_loglik(ctx, [A], pt.Trees([e]), b, precision=pt.PT_FP64)
-            want = oc.loglik(oc.Data.from_alignment(aln), e, b)
-            assert abs(l[0] - want) <= 1e-6 * abs(want)
+def test_67_taxa_four_categories(ctx):
+    """The paper's largest taxon count: lnL on both passes, full optimisation
+    in both precisions and the gradient, against the oracle."""
+    import torch
+    rng = np.random.default_rng(92)
+    n = 67
+    e, b = synth.yule_tree(n, rng, mean=0.05)
+    aln = synth.make_alignment(e, b, n, 600, rng, alpha=0.5, n_cats=4)
+    A = pt.Alignment.from_synth(ctx, aln)
+    D = oc.Data.from_alignment(aln)
+    ne, nb, _ = pt.pt_nni_neighbors(n, e, b)
+    pick = [0, 64, 127]
+    T = pt.Trees([ne[i] for i in pick])
+    lens = np.concatenate([nb[i] for i in pick])
+    want = np.array([oc.loglik(D, ne[i], nb[i]) for i in pick])
+    dev = torch.device("cuda:0")
+    for prec in (pt.PT_FP64, pt.PT_FP32):
+        for path in (pt.PT_LOGLIK_REGISTERS, pt.PT_LOGLIK_STORED):
+            plan = pt.Plan(ctx, [A], T, pt.PT_PLAN_LOGLIK, prec)
+            plan.set_loglik_path(path)
+            d_b = torch.tensor(lens, dtype=torch.float64, device=dev)
+            d_l = torch.zeros(len(pick), dtype=torch.float64, device=dev)
+            plan.loglik(d_b, d_l)
+            torch.cuda.synchronize()
+            got = d_l.cpu().numpy()
+            plan.close()
+            say("67 taxa lnL prec", prec, "path", path, "max abs", np.max(np.abs(got - want)))
+            if prec == pt.PT_FP64 or path == pt.PT_LOGLIK_REGISTERS:
+                assert np.max(np.abs(got - want) / np.abs(want)) < 1e-11
+            else:
+                assert np.max(np.abs(got - want)) < 1e-4
+    wo = np.array([oc.optimize(D, ne[i], nb[i])[0] for i in pick])
+    for prec in (pt.PT_FP64, pt.PT_FP32):
+        lo, _, _, st = pt.pt_batch_optimize_branches(ctx, [A], T, lens, precision=prec)
+        say("67 taxa optimum prec", prec, "vs oracle", lo - wo)
+        assert np.all(st == 0)
+        if prec == pt.PT_FP64:
+            assert np.max(np.abs(lo - wo) / np.abs(wo)) < 1e-6
         else:
-            with pytest.raises(pt.PTError) as ei:
-                pt.pt_batch_loglik(ctx, [A], pt.Trees([e]), b, precision=pt.PT_FP64)
-            assert ei.value.code == PT_EUNSUPPORTED
+            assert np.max(np.abs(lo - wo)) < 1e-4
+    _, g, _ = pt.pt_batch_branch_grad(ctx, [A], T, lens, pt.PT_FP64)
+    gw = np.concatenate([oc.gradient(D, ne[i], nb[i])[1] for i in pick])
+    assert np.max(np.abs(g - gw) / np.maximum(1.0, np.abs(gw))) < 1e-7
+
+
+def test_lds_limit(ctx):
+    """150 taxa with eight categories: the FP64 matrices (297 edges x 8 x 128
+    bytes, about 300 KB) exceed any LDS, so optimisation is refused; the lnL
+    runs on the register-resident pass where the device's LDS holds its
+    stack, and is otherwise refused, never wrong."""
+    rng = np.random.default_rng(93)
+    n = 150
+    e, b = synth.yule_tree(n, rng, mean=0.05)
+    aln = synth.make_alignment(e, b, n, 200, rng, alpha=0.5, n_cats=8)
+    A = pt.Alignment.from_synth(ctx, aln)
+    for prec in (pt.PT_FP64, pt.PT_FP32):
+        with pytest.raises(pt.PTError) as ei:
+            pt.pt_batch_optimize_branches(ctx, [A], pt.Trees([e]), b, precision=prec)
+        assert ei.value.code == PT_EUNSUPPORTED
+    want = oc.loglik(oc.Data.from_alignment(aln), e, b)
+    try:
+        got = pt.pt_batch_loglik(ctx, [A], pt.Trees([e]), b, precision=pt.PT_FP64)[0]
+    except pt.PTError as err:
+        assert err.code == PT_EUNSUPPORTED, err
+        say("150 taxa x 8 categories lnL refused:", err)
+        return
+    say("150 taxa x 8 categories lnL", got, "oracle", want)
+    assert abs(got - want) <= 1e-11 * abs(want)

@@ -209,3 +209,60 @@ def test_optimize_c2_full_batch_as_benchmarked(ctx):
                 else:
                     assert np.max(np.abs(got - ref)) < tol
         plan.close()
+
+
+@pytest.mark.parametrize("path", ["registers", "stored"])
+def test_loglik_paths_uneven_batch(ctx, path):
+    """Both lnL passes on one plan over uneven alignments (n 2..40, patterns
+    1 to 1200, K 1..8 in one layout, several tiles with ragged tails): the
+    register-resident pass (no partial stored, FP64 in either precision) and
+    the stored post-order pass."""
+    import torch
+    specs = [(2, 50, 1), (3, 300, 4), (4, 1, 2), (9, 700, 3), (17, 257, 8), (40, 1200, 4), (12, 513, 5)]
+    code = pt.PT_LOGLIK_REGISTERS if path == "registers" else pt.PT_LOGLIK_STORED
+    dev = torch.device("cuda:0")
+    alns, edges, lens, want, idx = [], [], [], [], []
+    rng = np.random.default_rng(70)
+    for i, (n, S, k) in enumerate(specs):
+        e, b, a = case(n, S, 200 + i, K=k, mean=0.1)
+        alns.append(a)
+        for rep in range(2):
+            bb = b * rng.uniform(0.5, 1.5, size=len(b))
+            idx.append(i)
+            edges.append(e)
+            lens.append(bb)
+            want.append(oc.loglik(oc.Data.from_alignment(a), e, bb))
+    A = [pt.Alignment.from_synth(ctx, a) for a in alns]
+    T = pt.Trees(edges, idx)
+    want = np.array(want)
+    for prec in (pt.PT_FP64, pt.PT_FP32):
+        plan = pt.Plan(ctx, A, T, pt.PT_PLAN_LOGLIK, prec)
+        plan.set_loglik_path(code)
+        d_b = torch.tensor(np.concatenate(lens), dtype=torch.float64, device=dev)
+        d_l = torch.zeros(T.n_trees, dtype=torch.float64, device=dev)
+        plan.loglik(d_b, d_l)
+        torch.cuda.synchronize()
+        got = d_l.cpu().numpy()
+        plan.close()
+        say(path, "prec", prec, "max abs", np.max(np.abs(got - want)))
+        if prec == pt.PT_FP64 or path == "registers":
+            assert np.max(np.abs(got - want) / np.abs(want)) < 1e-11
+        else:
+            assert np.max(np.abs(got - want)) < FP32_ABS
+
+
+def test_loglik_path_errors(ctx):
+    rng = np.random.default_rng(71)
+    e, b = synth.yule_tree(6, rng)
+    aln = synth.make_alignment(e, b, 6, 50, rng)
+    A = pt.Alignment.from_synth(ctx, aln)
+    plan = pt.Plan(ctx, [A], pt.Trees([e]), pt.PT_PLAN_LOGLIK, pt.PT_FP64)
+    with pytest.raises(pt.PTError) as ei:
+        plan.set_loglik_path(7)
+    assert ei.value.code == -1
+    plan.close()
+    plan = pt.Plan(ctx, [A], pt.Trees([e]), pt.PT_PLAN_OPTIMIZE, pt.PT_FP64)
+    with pytest.raises(pt.PTError) as ei:
+        plan.set_loglik_path(pt.PT_LOGLIK_STORED)
+    assert ei.value.code == -1
+    plan.close()

@@ -107,3 +107,61 @@ def test_search_rejects_bad_settings():
         OracleSearch(None, 6, threshold=-1.0, radius=-2)
     with pytest.raises(ValueError):
         OracleSearch(None, 6, threshold=-1.0, radius=0.5)
+
+
+def paper_loop(D, n, start, T, radius):
+    """The topographer's loop written out one topology at a time (Methods,
+    "Phylogenetic Topographer"): pop the next todo entry; skip it if
+    visited; otherwise visit it (optimise every length), update lmax, and if
+    its lnL is at least lmax + T, record it as good and, for each of its
+    NNI neighbours not yet visited, optimise the lengths within the radius
+    of the new edge and push it onto todo when that lnL is at least
+    lmax + T.  The good set is filtered by the final lmax + T."""
+    from paper_1811_11007_amd import _lib as Lh
+    E = 2 * n - 3
+    todo = [(topo.key(start[0], n), start[0], start[1])]
+    visited, good = set(), {}
+    lmax = -np.inf
+    head = 0
+    while head < len(todo):
+        k, e, b = todo[head]
+        head += 1
+        if k in visited:
+            continue
+        visited.add(k)
+        l, bo, _, _ = oc.optimize(D, e, b)
+        lmax = max(lmax, l)
+        if l < lmax + T:
+            continue
+        good[k] = l
+        ne, nb, tt = Lh.pt_nni_neighbors(n, np.asarray(e, np.int32), bo)
+        for j in range(len(ne)):
+            kk = topo.key(ne[j], n)
+            if kk in visited:
+                continue
+            mask = None
+            if radius >= 0:
+                mask = np.zeros(E, np.uint8)
+                mask[sorted(topo.radius_edges(ne[j], n, int(tt[j][0]), radius))] = 1
+            lp, bp, _, _ = oc.optimize(D, ne[j], nb[j], mask=mask)
+            if lp >= lmax + T:
+                todo.append((kk, ne[j], bp))
+    return {k for k, l in good.items() if l >= lmax + T}
+
+
+@pytest.mark.parametrize("radius", [0, 1])
+def test_search_matches_the_papers_loop(radius):
+    """One topology per batch, the batched search gives the good set of the
+    loop written out step by step; in particular a neighbour rejected from
+    one parent's lengths can still be queued from a later parent's."""
+    n = 6
+    rng = np.random.default_rng(73)
+    e, b = synth.yule_tree(n, rng, mean=0.15)
+    aln = synth.make_alignment(e, b, n, 150, rng, alpha=0.5, n_cats=4)
+    D = oc.Data.from_alignment(aln)
+    start = (e, np.full(2 * n - 3, 0.1))
+    T = -6.0
+    want = paper_loop(D, n, start, T, radius)
+    s = OracleSearch(D, n, threshold=T, radius=radius, batch=1)
+    got = {topo.key(v[1], n) for v in s.run([start]).good.values()}
+    assert got == want
