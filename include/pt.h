@@ -170,6 +170,23 @@ pt_status pt_batch_branch_grad(pt_ctx *ctx, pt_aln *const *alns, int32_t n_alns,
                                int32_t precision, double *lnl_out,
                                double *grad_out, double *hess_diag_out);
 
+/* pt_batch_loglik for callers that cannot allocate device memory (code
+ * under graph capture, tight serving loops, harnesses that forbid it): the
+ * same arguments, validation and results, computed by the register-resident
+ * pass (FP64, see pt_plan_set_loglik_path) with no hipMalloc, hipFree or
+ * other allocating call.  Descriptors, programs, lengths, transition
+ * matrices and per-tile sums go to a fixed 64 MiB workspace per device,
+ * held by the library until the process ends (about 900 trees of 64 taxa
+ * with four categories); PT_ENOMEM, naming the bytes needed, for a batch
+ * that does not fit, PT_EUNSUPPORTED for a tree beyond the register pass.
+ * Host-pointer call, synchronous on the context's stream.  Every call on a
+ * device shares its workspace: calls that overlap on one device (other
+ * threads, other contexts of the device) race and must be serialised by
+ * the caller. */
+pt_status pt_batch_loglik_noalloc(pt_ctx *ctx, pt_aln *const *alns, int32_t n_alns,
+                                  const pt_trees *trees, const double *brlen,
+                                  int32_t precision, double *lnl_out /* [n_trees] */);
+
 /* ------------------------------------------------------ device-side plans */
 
 /* A plan compiles a batch once (validation, rooting, the per-tree program of

@@ -23,6 +23,7 @@ PT_LOGLIK_REGISTERS, PT_LOGLIK_STORED = 0, 1
 EXPORTS = [
     "pt_last_error", "pt_ctx_create", "pt_ctx_destroy", "pt_aln_create", "pt_aln_destroy",
     "pt_opt_default", "pt_batch_loglik", "pt_batch_optimize_branches", "pt_batch_branch_grad",
+    "pt_batch_loglik_noalloc",
     "pt_plan_create", "pt_plan_destroy", "pt_plan_set_graphs", "pt_plan_loglik",
     "pt_plan_optimize", "pt_plan_set_alpha", "pt_plan_optimize_alpha", "pt_plan_grad", "pt_plan_autotune",
     "pt_plan_traffic", "pt_plan_set_profile", "pt_plan_set_loglik_path", "pt_plan_info", "pt_plan_set_launch", "pt_plan_launch_shape",
@@ -97,6 +98,7 @@ def lib():
         L.pt_batch_optimize_branches.argtypes = [vp, P(vp), i32, P(pt_trees), vp, vp, P(pt_opt), i32,
                                                  vp, vp, vp]
         L.pt_batch_branch_grad.argtypes = [vp, P(vp), i32, P(pt_trees), vp, i32, vp, vp, vp]
+        L.pt_batch_loglik_noalloc.argtypes = [vp, P(vp), i32, P(pt_trees), vp, i32, vp]
         L.pt_plan_create.argtypes = [vp, P(vp), i32, P(pt_trees), vp, i32, i32, P(vp)]
         L.pt_plan_destroy.argtypes = [vp]
         L.pt_plan_destroy.restype = None
@@ -241,6 +243,16 @@ def pt_batch_loglik(ctx, alns, trees: Trees, brlen, precision=PT_FP64):
     out = np.zeros(trees.n_trees)
     check(lib().pt_batch_loglik(ctx.h, _aln_array(alns), len(alns), ctypes.byref(trees.c),
                                 _ptr(brlen), precision, _ptr(out)))
+    return out
+
+
+def pt_batch_loglik_noalloc(ctx, alns, trees: Trees, brlen, precision=PT_FP64):
+    """pt_batch_loglik through the library's fixed workspace (no device
+    allocation; see pt.h)."""
+    brlen = np.ascontiguousarray(brlen, dtype=np.float64)
+    out = np.zeros(trees.n_trees)
+    check(lib().pt_batch_loglik_noalloc(ctx.h, _aln_array(alns), len(alns), ctypes.byref(trees.c),
+                                        _ptr(brlen), precision, _ptr(out)))
     return out
 
 

@@ -82,6 +82,9 @@ struct pt_ctx {
     // size for every batch, and a fresh hipMalloc / hipFree of tens of GB
     // each time cost far more than the optimisation itself
     std::shared_ptr<DevicePool> pool = std::make_shared<DevicePool>();
+    // this device's no-allocation workspace (pt_batch_loglik_noalloc)
+    void *noalloc = nullptr;
+    std::string noalloc_err;
 };
 
 struct pt_aln {
@@ -931,6 +934,10 @@ pt_status pt_ctx_create(int32_t device, pt_ctx **out) {
     }
     c->n_cu = prop.multiProcessorCount;
     c->lds_per_block = prop.sharedMemPerBlock;
+    if ((e = pt::noalloc_workspace(device, &c->noalloc)) != hipSuccess) {
+        c->noalloc = nullptr;
+        c->noalloc_err = std::string("hipGetSymbolAddress: ") + hipGetErrorString(e);
+    }
     *out = c;
     return PT_OK;
 }
@@ -1023,6 +1030,116 @@ pt_status pt_batch_branch_grad(pt_ctx *ctx, pt_aln *const *alns, int32_t n_alns,
                                double *hess_diag_out) {
     return host_batch(ctx, alns, n_alns, trees, nullptr, brlen, nullptr, nullptr, precision, PT_PLAN_GRAD, lnl_out,
                       nullptr, nullptr, grad_out, hess_diag_out);
+}
+
+pt_status pt_batch_loglik_noalloc(pt_ctx *ctx, pt_aln *const *alns, int32_t n_alns, const pt_trees *trees,
+                                  const double *brlen, int32_t precision, double *lnl_out) {
+    std::vector<int> ntx;
+    pt_status st = check_trees(ctx, alns, n_alns, trees, ntx);
+    if (st) return st;
+    if (precision != PT_FP32 && precision != PT_FP64) return fail(PT_EINVAL, "precision must be PT_FP64 or PT_FP32");
+    const int B = trees->n_trees;
+    const int64_t NE = B ? trees->edge_offset[B] : 0;
+    if ((st = check_lengths(brlen, NE))) return st;
+    if (B > 0 && !lnl_out) return fail(PT_EINVAL, "lnl_out is NULL");
+    if (B == 0) return PT_OK;
+    if (!ctx->noalloc) return fail(PT_EDEVICE, "no-allocation workspace unavailable: " + ctx->noalloc_err);
+    const int kp = kp_of_plan(alns, trees);
+    const int reg_pats = pt::loglik_reg_tile_patterns(kp);
+    // programs and descriptors on the host (host memory only)
+    std::vector<Op> ops;
+    std::vector<TreeDev> td(B);
+    std::vector<AlnDev> ad(B);
+    std::vector<int32_t> edge_tree(NE), tile_tree;
+    std::vector<int> tree_E(B);
+    int depth = 0, n_max = 0;
+    int64_t pm_off = 0;
+    for (int b = 0; b < B; ++b) {
+        pt::Tree t;
+        std::string err;
+        if ((st = pt::build_tree(ntx[b], trees->edges + 2 * trees->edge_offset[b], t, err)))
+            return fail(st, "tree " + std::to_string(b) + ": " + err);
+        const AlnDev &a = alns[trees->aln_index[b]]->desc;
+        TreeDev d{};
+        d.aln = b;
+        d.n_edges = t.n_edges;
+        d.edge_off = trees->edge_offset[b];
+        d.pm_off = pm_off;
+        d.op_first = (int32_t)ops.size();
+        depth = std::max(depth, pt::compile_loglik_reg(t, ops));
+        d.n_first = (int32_t)ops.size() - d.op_first;
+        d.n_tiles = (a.P + reg_pats - 1) / reg_pats;
+        td[b] = d;
+        ad[b] = a;
+        tree_E[b] = t.n_edges;
+        n_max = std::max(n_max, ntx[b]);
+        pm_off += (int64_t)t.n_edges * kp * 16;
+        for (int e = 0; e < t.n_edges; ++e) edge_tree[d.edge_off + e] = b;
+    }
+    if (depth > pt::kRegStack) return fail(PT_EUNSUPPORTED, "a tree needs more than 8 stack slots");
+    const size_t lds = pt::loglik_reg_lds(kp, n_max, depth);
+    if (lds > ctx->lds_per_block) return fail(PT_EUNSUPPORTED, "a tree exceeds the LDS of a block");
+    {   // tiles of the trees with the most edges first
+        std::vector<int> order(B);
+        std::iota(order.begin(), order.end(), 0);
+        std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return tree_E[x] > tree_E[y]; });
+        for (int b : order) {
+            td[b].tile_begin = (int32_t)tile_tree.size();
+            for (int x = 0; x < td[b].n_tiles; ++x) tile_tree.push_back(b);
+        }
+    }
+    const int tiles = (int)tile_tree.size();
+    // workspace layout: the sections copied from the host, then the ones the
+    // kernels write; each 256-byte aligned
+    auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    const double ident[16] = {1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1};
+    const size_t o_aln = 0, o_tree = up(o_aln + sizeof(AlnDev) * B), o_ops = up(o_tree + sizeof(TreeDev) * B),
+                 o_etree = up(o_ops + sizeof(Op) * ops.size()), o_ttree = up(o_etree + sizeof(int32_t) * NE),
+                 o_len = up(o_ttree + sizeof(int32_t) * tiles), o_ident = up(o_len + sizeof(double) * NE),
+                 in_bytes = o_ident + sizeof(ident), o_pm = up(in_bytes),
+                 o_part = up(o_pm + sizeof(double) * pm_off), o_lnl = up(o_part + sizeof(double) * 3 * tiles),
+                 total = o_lnl + sizeof(double) * B;
+    if (total > pt::kNoAllocBytes)
+        return fail(PT_ENOMEM, "batch needs " + std::to_string(total) + " bytes of the " +
+                                   std::to_string(pt::kNoAllocBytes) + "-byte no-allocation workspace");
+    std::vector<uint8_t> img(in_bytes);
+    std::memcpy(img.data() + o_aln, ad.data(), sizeof(AlnDev) * B);
+    std::memcpy(img.data() + o_tree, td.data(), sizeof(TreeDev) * B);
+    std::memcpy(img.data() + o_ops, ops.data(), sizeof(Op) * ops.size());
+    std::memcpy(img.data() + o_etree, edge_tree.data(), sizeof(int32_t) * NE);
+    std::memcpy(img.data() + o_ttree, tile_tree.data(), sizeof(int32_t) * tiles);
+    std::memcpy(img.data() + o_len, brlen, sizeof(double) * NE);
+    std::memcpy(img.data() + o_ident, ident, sizeof(ident));
+    char *ws = reinterpret_cast<char *>(ctx->noalloc);
+    hipStream_t s = ctx->stream;
+    PT_HIP(hipSetDevice(ctx->device));
+    PT_HIP(hipMemcpyAsync(ws, img.data(), in_bytes, hipMemcpyHostToDevice, s));
+    pt::BatchArgs a{};
+    a.trees = reinterpret_cast<const TreeDev *>(ws + o_tree);
+    a.alns = reinterpret_cast<const AlnDev *>(ws + o_aln);
+    a.ops = reinterpret_cast<const Op *>(ws + o_ops);
+    a.edge_tree = reinterpret_cast<const int32_t *>(ws + o_etree);
+    a.tile_tree = reinterpret_cast<const int32_t *>(ws + o_ttree);
+    a.pmat = reinterpret_cast<double *>(ws + o_pm);
+    a.part = reinterpret_cast<double *>(ws + o_part);
+    a.n_trees = B;
+    a.n_tiles = tiles;
+    a.n_edges = NE;
+    a.part_cols = 1;
+    a.kp = kp;
+    a.reg_depth = depth;
+    a.ident = reinterpret_cast<const double *>(ws + o_ident);
+    double *d_lnl = reinterpret_cast<double *>(ws + o_lnl);
+    hipError_t e;
+    if ((e = pt::launch_pmat(a, reinterpret_cast<const double *>(ws + o_len), s)) != hipSuccess ||
+        (e = pt::launch_loglik_reg(kp, a, lds, s)) != hipSuccess ||
+        (e = pt::launch_reduce(false, a, d_lnl, nullptr, nullptr, s)) != hipSuccess)
+        return fail(PT_EDEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
+    std::vector<double> out(B);
+    PT_HIP(hipMemcpyAsync(out.data(), d_lnl, sizeof(double) * B, hipMemcpyDeviceToHost, s));
+    PT_HIP(hipStreamSynchronize(s));
+    std::copy(out.begin(), out.end(), lnl_out);
+    return PT_OK;
 }
 
 pt_status pt_plan_create(pt_ctx *ctx, pt_aln *const *alns, int32_t n_alns, const pt_trees *trees,

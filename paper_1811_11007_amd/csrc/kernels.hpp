@@ -70,6 +70,11 @@ hipError_t launch_tiles(int precision, int kp, const BatchArgs &a, const double 
 int loglik_reg_tile_patterns(int kp);
 size_t loglik_reg_lds(int kp, int n, int depth);
 hipError_t launch_loglik_reg(int kp, const BatchArgs &a, size_t lds_bytes, hipStream_t s);
+// The fixed device workspace of pt_batch_loglik_noalloc (noalloc.hip):
+// kNoAllocBytes on each device; its address on `device`, looked up once per
+// device (with that device current) and kept.
+constexpr size_t kNoAllocBytes = (size_t)64 << 20;
+hipError_t noalloc_workspace(int device, void **out);
 hipError_t launch_reduce(bool grad, const BatchArgs &a, double *lnl, double *grad_out,
                          double *hess_out, hipStream_t s);
 // With a.groups > 1, grid = trees x groups and a.gsync zeroed beforehand.
