@@ -1198,24 +1198,27 @@ __global__ void k_reduce(const BatchArgs a, bool grad, double *lnl, double *gout
 // ------------------------------------------------ register-resident lnL
 //
 // The lnL of a tree by Felsenstein's post-order pass with no partial ever
-// stored: a lane owns one pattern and one rate category, and its partials
-// live in registers (an accumulator and a stack of kRegStack slots, the
-// program ordered so that the stack stays shallow, see compile_loglik_reg).
-// A wave is one category of 64 patterns, so every transition-matrix entry
-// it reads is wave-uniform and arrives by scalar loads (k_pmat writes the
-// matrices before the launch).  Arithmetic is FP64 whatever the storage
-// precision of the plan, because nothing is stored.  Scaling is per lane
-// (per pattern and category): a partial whose largest entry falls below
-// 2^-256 is multiplied by 2^256 and the lane counts the event; all events of
-// a lane multiply into its root value, so one counter per lane suffices.
-// At the root edge the categories of a pattern meet in LDS:
+// stored: a lane owns kItems patterns of one rate category, and their
+// partials live in registers (an accumulator per pattern) and a small stack
+// in LDS, the program ordered so that the stack stays shallow (see
+// compile_loglik_reg).  A wave is one category, so every transition-matrix
+// entry it reads is wave-uniform and arrives by scalar loads (k_pmat writes
+// the matrices before the launch), and each entry loaded serves the lane's
+// kItems patterns.  Arithmetic is FP64 whatever the storage precision of
+// the plan, because nothing is stored.  Scaling is per pattern and
+// category: a partial whose largest entry falls below 2^-256 is multiplied
+// by 2^256 and the event counted; all events of a pattern and category
+// multiply into its root value, so one counter per pattern suffices.  At the
+// root edge the categories of a pattern meet in LDS:
 //   ln L_p = ln sum_k 2^(-256 (c_k - c_min)) L_k - ln K - 256 c_min ln 2.
 // Memory traffic per pattern: the n tip codes and the weight.
 template <int KP>
 struct RegShape {
+    static constexpr int kItems = 2;                        // patterns per lane
     static constexpr int kWaves = KP >= 4 ? KP : 4;        // waves per block
-    static constexpr int kGroups = kWaves / KP;             // 64-pattern groups per block
-    static constexpr int kPats = 64 * kGroups;              // patterns per tile
+    static constexpr int kGroups = kWaves / KP;             // pattern groups per block
+    static constexpr int kGroupPats = 64 * kItems;          // patterns of a group
+    static constexpr int kPats = kGroupPats * kGroups;      // patterns per tile
     static constexpr int kThreads = 64 * kWaves;
 };
 
@@ -1223,18 +1226,19 @@ __device__ inline void reg_copy(double d[4], const double s[4]) {
     d[0] = s[0]; d[1] = s[1]; d[2] = s[2]; d[3] = s[3];
 }
 
-// The stack lives in LDS, [slot][thread] of four doubles (a stack indexed by
-// a runtime slot number does not stay in registers); the accumulator, which
-// most steps read and write, is in registers.
+// The stack lives in LDS, [slot][item][thread] of four doubles (a stack
+// indexed by a runtime slot number does not stay in registers); the
+// accumulators, which most steps read and write, are in registers.
 template <int KP>
 __global__ void __launch_bounds__(RegShape<KP>::kThreads) k_loglik_reg(const BatchArgs a) {
     using RS = RegShape<KP>;
-    // dynamic LDS: the stack [kRegStack or fewer][kThreads] of double4, then
-    // the tile's tip codes [n][kPats]
+    constexpr int NI = RS::kItems;
+    // dynamic LDS: the stack [kRegStack or fewer][kItems][kThreads] of
+    // double4, then the tile's tip codes [n][kPats]
     extern __shared__ double4 stack_lds[];
-    uint8_t *tip_lds = reinterpret_cast<uint8_t *>(stack_lds + (size_t)a.reg_depth * RS::kThreads);
-    __shared__ double cat_l[RS::kWaves][64];
-    __shared__ int cat_c[RS::kWaves][64];
+    uint8_t *tip_lds = reinterpret_cast<uint8_t *>(stack_lds + (size_t)a.reg_depth * NI * RS::kThreads);
+    __shared__ double cat_l[RS::kWaves][RS::kGroupPats];
+    __shared__ int cat_c[RS::kWaves][RS::kGroupPats];
     __shared__ double grp_sum[RS::kGroups];
     const int tile = blockIdx.x;
     const TreeDev td = a.trees[a.tile_tree[tile]];
@@ -1251,7 +1255,8 @@ __global__ void __launch_bounds__(RegShape<KP>::kThreads) k_loglik_reg(const Bat
         tip_lds[x] = q < P ? ldg(aln->tips + (size_t)tx * P + q) : (uint8_t)15;
     }
     __syncthreads();
-    const uint8_t *tips = tip_lds + grp * 64 + lane;
+    // item j of this lane: pattern p0 + grp * kGroupPats + j * 64 + lane
+    const uint8_t *tips = tip_lds + grp * RS::kGroupPats + lane;
     // this wave's category of every edge: P(r_k t_e) at pm + e * KP * 16
     const __attribute__((address_space(4))) double *pm =
         (const __attribute__((address_space(4))) double *)(a.pmat + td.pm_off) + k * 16;
@@ -1261,18 +1266,22 @@ __global__ void __launch_bounds__(RegShape<KP>::kThreads) k_loglik_reg(const Bat
     const __attribute__((address_space(4))) double *ident =
         (const __attribute__((address_space(4))) double *)a.ident;
     const double thr = ldexp(1.0, -256), up = ldexp(1.0, 256);
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    double4 *stk = stack_lds + threadIdx.x;
-    int cnt = 0;
-    double L = 0.0;
-    // One step of the program.  The compiler emits three side forms (see
+    double acc[NI][4];
+    int cnt[NI];
+    double L[NI];
+#pragma unroll
+    for (int j = 0; j < NI; ++j) {
+        reg_copy(acc[j], (const double[4]){0.0, 0.0, 0.0, 0.0});
+        cnt[j] = 0;
+        L[j] = 0.0;
+    }
+    double4 *stk = stack_lds + threadIdx.x;  // item j, slot s at stk[(s * NI + j) * kThreads]
+    // One step for item j.  The compiler emits three side forms (see
     // compile_loglik_reg): two tips; the accumulator and a tip; a stack slot
     // and the accumulator.  Each form has its own straight-line code so that
     // the step's scalar matrix loads and LDS reads all issue before the one
-    // wait for them.
-    // (an OP_REVAL's side a takes the identity matrix: ea < 0, see below)
-    auto step = [&](const Op &op, const double xa[4], const double xb[4], const double *ma, const double *mb,
-                    bool upd) {
+    // wait for them.  (An OP_REVAL's side a takes the identity matrix: ea < 0.)
+    auto step = [&](int j, const double xa[4], const double xb[4], const double *ma, const double *mb, bool upd) {
         double y[4], mx = 0.0;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -1284,13 +1293,13 @@ __global__ void __launch_bounds__(RegShape<KP>::kThreads) k_loglik_reg(const Bat
             mx = fmax(mx, y[i]);
         }
         if (!upd) {
-            L = aln->freqs[0] * y[0] + aln->freqs[1] * y[1] + aln->freqs[2] * y[2] + aln->freqs[3] * y[3];
+            L[j] = aln->freqs[0] * y[0] + aln->freqs[1] * y[1] + aln->freqs[2] * y[2] + aln->freqs[3] * y[3];
             return;
         }
         const bool scale = mx < thr && mx > 0.0;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) acc[i] = scale ? y[i] * up : y[i];
-        cnt += scale ? 1 : 0;
+        for (int i = 0; i < 4; ++i) acc[j][i] = scale ? y[i] * up : y[i];
+        cnt[j] += scale ? 1 : 0;
     };
     // each op is loaded one step ahead, so its scalar load's round trip
     // overlaps the previous step
@@ -1299,68 +1308,96 @@ __global__ void __launch_bounds__(RegShape<KP>::kThreads) k_loglik_reg(const Bat
         const Op op = nx;
         if (o + 1 < td.n_first) nx = a.ops[td.op_first + o + 1];
         if (op.code == OP_RPUSH) {
-            stk[(size_t)op.dst * RS::kThreads] = make_double4(acc[0], acc[1], acc[2], acc[3]);
+#pragma unroll
+            for (int j = 0; j < NI; ++j)
+                stk[((size_t)op.dst * NI + j) * RS::kThreads] = make_double4(acc[j][0], acc[j][1], acc[j][2], acc[j][3]);
             continue;
         }
         // both matrices are used on every path, so their loads issue together
         const bool upd = op.code == OP_RUPDATE;
         const auto Pa = op.ea >= 0 ? pm + (size_t)op.ea * KP * 16 : ident;
         const auto Pb = pm + (size_t)op.eb * KP * 16;
-        double ma[16], mb[16], xa[4], xb[4];
+        double ma[16], mb[16];
         if (op.a >= 0) {  // two tips
-            const unsigned ca = tips[op.a * RS::kPats], cb = tips[op.b * RS::kPats];
+            unsigned ca[NI], cb[NI];
+#pragma unroll
+            for (int j = 0; j < NI; ++j) {
+                ca[j] = tips[op.a * RS::kPats + j * 64];
+                cb[j] = tips[op.b * RS::kPats + j * 64];
+            }
 #pragma unroll
             for (int x = 0; x < 16; ++x) {
                 ma[x] = Pa[x];
                 mb[x] = Pb[x];
             }
-            tip_vec(ca, xa);
-            tip_vec(cb, xb);
-            step(op, xa, xb, ma, mb, upd);
+#pragma unroll
+            for (int j = 0; j < NI; ++j) {
+                double xa[4], xb[4];
+                tip_vec(ca[j], xa);
+                tip_vec(cb[j], xb);
+                step(j, xa, xb, ma, mb, upd);
+            }
         } else if (op.a == REF_ACC) {  // the accumulator and a tip
-            const unsigned cb = tips[op.b * RS::kPats];
+            unsigned cb[NI];
+#pragma unroll
+            for (int j = 0; j < NI; ++j) cb[j] = tips[op.b * RS::kPats + j * 64];
 #pragma unroll
             for (int x = 0; x < 16; ++x) {
                 ma[x] = Pa[x];
                 mb[x] = Pb[x];
             }
-            reg_copy(xa, acc);
-            tip_vec(cb, xb);
-            step(op, xa, xb, ma, mb, upd);
+#pragma unroll
+            for (int j = 0; j < NI; ++j) {
+                double xa[4], xb[4];
+                reg_copy(xa, acc[j]);
+                tip_vec(cb[j], xb);
+                step(j, xa, xb, ma, mb, upd);
+            }
         } else {  // a stack slot and the accumulator
-            const double4 v = stk[(size_t)(REF_STACK0 - op.a) * RS::kThreads];
+            double4 v[NI];
+#pragma unroll
+            for (int j = 0; j < NI; ++j) v[j] = stk[((size_t)(REF_STACK0 - op.a) * NI + j) * RS::kThreads];
 #pragma unroll
             for (int x = 0; x < 16; ++x) {
                 ma[x] = Pa[x];
                 mb[x] = Pb[x];
             }
-            xa[0] = v.x; xa[1] = v.y; xa[2] = v.z; xa[3] = v.w;
-            reg_copy(xb, acc);
-            step(op, xa, xb, ma, mb, upd);
+#pragma unroll
+            for (int j = 0; j < NI; ++j) {
+                double xa[4] = {v[j].x, v[j].y, v[j].z, v[j].w}, xb[4];
+                reg_copy(xb, acc[j]);
+                step(j, xa, xb, ma, mb, upd);
+            }
         }
     }
     // the categories of each pattern meet in LDS
-    cat_l[wave][lane] = L;
-    cat_c[wave][lane] = cnt;
+#pragma unroll
+    for (int j = 0; j < NI; ++j) {
+        cat_l[wave][j * 64 + lane] = L[j];
+        cat_c[wave][j * 64 + lane] = cnt[j];
+    }
     __syncthreads();
     if (k == 0) {
-        const int p = p0 + grp * 64 + lane;
         double term = 0.0;
-        if (p < P) {
-            int cmin = cat_c[wave][lane];
-            for (int c = 1; c < K; ++c) cmin = min(cmin, cat_c[wave + c][lane]);
-            double s = 0.0;
-            for (int c = 0; c < K; ++c) s += ldexp(cat_l[wave + c][lane], -256 * (cat_c[wave + c][lane] - cmin));
-            term = ldg(aln->w + p) * (log(s) - log((double)K) - (double)cmin * 256.0 * kLn2);
+#pragma unroll
+        for (int j = 0; j < NI; ++j) {
+            const int q = j * 64 + lane, p = p0 + grp * RS::kGroupPats + q;
+            if (p < P) {
+                int cmin = cat_c[wave][q];
+                for (int c = 1; c < K; ++c) cmin = min(cmin, cat_c[wave + c][q]);
+                double sum = 0.0;
+                for (int c = 0; c < K; ++c) sum += ldexp(cat_l[wave + c][q], -256 * (cat_c[wave + c][q] - cmin));
+                term += ldg(aln->w + p) * (log(sum) - log((double)K) - (double)cmin * 256.0 * kLn2);
+            }
         }
         term = wave_sum(term);
         if (lane == 0) grp_sum[grp] = term;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        double s = 0.0;
-        for (int g = 0; g < RS::kGroups; ++g) s += grp_sum[g];
-        a.part[(size_t)tile * a.part_cols * 3] = s;
+        double sum = 0.0;
+        for (int g = 0; g < RS::kGroups; ++g) sum += grp_sum[g];
+        a.part[(size_t)tile * a.part_cols * 3] = sum;
     }
 }
 
@@ -1759,7 +1796,8 @@ int loglik_reg_tile_patterns(int kp) {
 }
 
 size_t loglik_reg_lds(int kp, int n, int depth) {
-    PT_KP_SWITCH(return (size_t)depth * RegShape<KP>::kThreads * sizeof(double4) + (size_t)n * RegShape<KP>::kPats);
+    PT_KP_SWITCH(return (size_t)depth * RegShape<KP>::kItems * RegShape<KP>::kThreads * sizeof(double4) +
+                        (size_t)n * RegShape<KP>::kPats);
     return 0;
 }
 
