@@ -1097,6 +1097,45 @@ __global__ void k_pmat(const BatchArgs a, const double *brlen) {
     }
 }
 
+// OP_UPDATE for one pattern per thread whose side `fwd_b ? b : a` is the
+// partial the previous update of this thread made, still in registers
+// (`last`): only the other side is loaded.  The new partial is stored and
+// kept in `last` for the next update.  The same expressions as
+// update_sides, so the partials are identical.
+template <typename T, int KP, bool TO, int PM>
+__device__ inline void update_forwarded(const TreeView<T> &v, const Op &op, bool fwd_b, int p,
+                                        Side<T, KP, false> &last) {
+    Side<T, KP, TO> so;
+    so.fetch(v, fwd_b ? op.a : op.b, p);
+    double o[KP][4];
+    const int c = fwd_b ? update_pattern<T, KP, PM>(v, op, so, last, o) : update_pattern<T, KP, PM>(v, op, last, so, o);
+#pragma unroll
+    for (int k = 0; k < KP; ++k) last.r[k] = Store<T>::pack(o[k]);
+    last.c = c;
+#pragma unroll
+    for (int k = 0; k < KP; ++k)
+        if (k < v.K) Store<T>::store_raw(slot_ptr<T, KP>(v, op.dst, k, p), last.r[k]);
+    v.cnt[(size_t)op.dst * v.P + p] = (uint16_t)c;
+}
+
+// OP_UPDATE for one pattern per thread with both sides loaded, keeping the
+// new partial in `last` (update_sides with the result kept).
+template <typename T, int KP, bool TA, bool TB, int PM>
+__device__ inline void update_keep(const TreeView<T> &v, const Op &op, int p, Side<T, KP, false> &last) {
+    Side<T, KP, TA> sa;
+    Side<T, KP, TB> sb;
+    sa.fetch(v, op.a, p);
+    sb.fetch(v, op.b, p);
+    double o[KP][4];
+    last.c = update_pattern<T, KP, PM>(v, op, sa, sb, o);
+#pragma unroll
+    for (int k = 0; k < KP; ++k) last.r[k] = Store<T>::pack(o[k]);
+#pragma unroll
+    for (int k = 0; k < KP; ++k)
+        if (k < v.K) Store<T>::store_raw(slot_ptr<T, KP>(v, op.dst, k, p), last.r[k]);
+    v.cnt[(size_t)op.dst * v.P + p] = (uint16_t)last.c;
+}
+
 // Pattern-tile kernels (k_tiles32 / k_tiles64 below): each block runs its tree's program over one tile of
 // BS * kTileItems patterns.  LOGLIK programs end in one EVAL (column 0);
 // GRAD programs EVAL every edge.  Output: part[tile][col] = (lnL, d1, d2).
@@ -1134,10 +1173,41 @@ __device__ inline void tiles_body(const BatchArgs &a, const double *brlen) {
     double *wx = wxs + (threadIdx.x >> 6) * kWx;
     const int base = (tile - td.tile_begin) * BS * kTileItems;
     int parity = 0;
+    // FP64 partials, one pattern per thread: a partial the previous update
+    // made is taken from registers when this update reads it (a post-order
+    // pass reads most partials right after making them), saving that load's
+    // round trip.  With FP32 partials the extra live registers cost more than
+    // the load (measured), so those updates load both sides.
+    constexpr int PMK = kConstPm ? kPmConst : kPmLds;
+    constexpr bool kForward = !kConstPm;
+    static_assert(kTileItems == 1, "partials are forwarded for one pattern per thread");
+    const int p = base + threadIdx.x;
+    const bool live_p = p < v.np;
+    Side<T, KP, false> last;
+    int last_dst = -1;
     for (int o = 0; o < td.n_first; ++o) {
         const Op op = a.ops[td.op_first + o];
+        if (op.code == OP_UPDATE && !kForward) {
+            do_update<T, BS, KP, PMK>(v, op, base, kTileItems);
+            continue;
+        }
         if (op.code == OP_UPDATE) {
-            do_update<T, BS, KP, kConstPm ? kPmConst : kPmLds>(v, op, base, kTileItems);
+            if (live_p) {
+                if (op.b >= 0 && op.b == last_dst) {
+                    if (op.a < 0) update_forwarded<T, KP, true, PMK>(v, op, true, p, last);
+                    else update_forwarded<T, KP, false, PMK>(v, op, true, p, last);
+                } else if (op.a >= 0 && op.a == last_dst) {
+                    if (op.b < 0) update_forwarded<T, KP, true, PMK>(v, op, false, p, last);
+                    else update_forwarded<T, KP, false, PMK>(v, op, false, p, last);
+                } else if (op.a < 0) {
+                    if (op.b < 0) update_keep<T, KP, true, true, PMK>(v, op, p, last);
+                    else update_keep<T, KP, true, false, PMK>(v, op, p, last);
+                } else {
+                    if (op.b < 0) update_keep<T, KP, false, true, PMK>(v, op, p, last);
+                    else update_keep<T, KP, false, false, PMK>(v, op, p, last);
+                }
+            }
+            last_dst = op.dst;
             continue;
         }
         const Sums3 r =

@@ -22,9 +22,12 @@ Topology identity is the library's canonical split key (sorted non-trivial
 splits as bitmasks), hashed on the host in Python sets and dicts.
 
 Starting lengths of a proposal are its parent's lengths carried through the
-move (cold start) or, with a warm start, the parent's lengths with the five
-edges the move touches replaced by the network's prediction.  A queued
-proposal carries its partially optimised lengths to its visit.
+move (cold start).  With a warm start, a proposal that the cold start's
+partial optimum leaves below the gate by at most warm_margin is optimised
+again from the parent's lengths with the five edges the move touches
+replaced by the network's prediction, and queued if that partial optimum
+passes the gate: the good set is then a superset of the cold search's.  A
+queued proposal carries its partially optimised lengths to its visit.
 """
 from __future__ import annotations
 
@@ -47,8 +50,8 @@ class SearchResult:
     full_time_s: float
     proposal_time_s: float
     batches: int
-    cold_redo: int = 0    # warm-started proposals near the gate optimised again from the cold start
-    cold_better: int = 0  # of those, the ones whose cold-started partial optimum was better
+    warm_tried: int = 0   # cold-rejected proposals within warm_margin of the gate, retried warm
+    warm_passed: int = 0  # of those, the ones whose warm-started partial optimum passed the gate
     samples: list = field(default_factory=list)  # (features, parent lengths, optimised lengths) of the
                                                  # five touched edges, when collecting
 
@@ -111,49 +114,45 @@ class ThresholdSearch:
         plan.close()
         return out
 
-    def _propose(self, chunk, radius, gate, stats):
-        """Partial optimisation of one chunk of proposals; returns (lnL per
-        proposal, lengths concatenated).  With a warm start each proposal
-        starts from the network's lengths; those whose warm lnL falls short
-        of the gate by at most warm_margin are optimised again from the
-        cold start (the parent's lengths) and keep the better result, so
-        the network decides alone only where the cold start is far from the
-        gate."""
+    def _propose(self, chunk, radius, stats, warm=False):
+        """Partial optimisation of one chunk of proposals, from the parent's
+        lengths (cold) or from the network's lengths for the five touched
+        edges (warm); returns (lnL per proposal, lengths concatenated)."""
         n = self.n
         E = 2 * n - 3
-        nc = len(chunk)
         trees = [p[1] for p in chunk]
         starts = np.concatenate([p[2] for p in chunk])
         masks = None
-        if radius >= 0:
+        if radius == "touched":
+            # the five edges the move touches, the rest held at the parent's
+            masks = []
+            for p in chunk:
+                m = np.zeros(E, np.uint8)
+                m[p[4]] = 1
+                masks.append(m)
+        elif radius >= 0:
             masks = list(L.pt_radius_masks(n, np.stack(trees), [p[4][0] for p in chunk], radius))
         t0 = time.perf_counter()
-        if self.warm is None:
-            lnl, bo, _ = self._optimize(trees, starts, masks)
-            stats["prop_time"] += time.perf_counter() - t0
-            return lnl, bo
-        X = np.stack([p[3] for p in chunk]).astype(np.float32)
-        pos = np.stack([i * E + p[4] for i, p in enumerate(chunk)]).astype(np.int32)
-        base = np.stack([p[5][p[4]] for p in chunk])
-        lnl, bo, _ = self._optimize(trees, starts, masks, (X, pos, base))
-        redo = [i for i in range(nc) if gate - self.warm_margin <= lnl[i] < gate]
-        stats["cold_redo"] = stats.get("cold_redo", 0) + len(redo)
-        if redo:
-            lc, bc, _ = self._optimize([trees[i] for i in redo], np.concatenate([chunk[i][2] for i in redo]),
-                                       None if masks is None else [masks[i] for i in redo])
-            for j, i in enumerate(redo):
-                if lc[j] > lnl[i]:
-                    lnl[i] = lc[j]
-                    bo[i * E:(i + 1) * E] = bc[j * E:(j + 1) * E]
-                    stats["cold_better"] = stats.get("cold_better", 0) + 1
+        rows = None
+        if warm:
+            X = np.stack([p[3] for p in chunk]).astype(np.float32)
+            pos = np.stack([i * E + p[4] for i, p in enumerate(chunk)]).astype(np.int32)
+            base = np.stack([p[5][p[4]] for p in chunk])
+            rows = (X, pos, base)
+        lnl, bo, _ = self._optimize(trees, starts, masks, rows)
         stats["prop_time"] += time.perf_counter() - t0
         return lnl, bo
 
-    def run(self, starts, collect=False, max_samples=None, progress=None):
-        """starts: list of (edges, brlen).  With collect, every proposal is
-        fully optimised and (features, parent and optimised lengths of the
-        five touched edges) are recorded for training.  progress, if given,
-        is called with a one-line summary after every batch of visits."""
+    def run(self, starts, collect=None, max_samples=None, progress=None):
+        """starts: list of (edges, brlen).  With collect = "full", every
+        proposal is fully optimised, with collect = "touched" its five
+        touched edges are optimised with the rest held at the parent's
+        lengths, and (features, parent and optimised lengths of the five
+        touched edges) are recorded for training; the proposal's gate uses
+        that optimum.  progress, if given, is called with a one-line summary
+        after every batch of visits."""
+        if collect not in (None, "full", "touched"):
+            raise ValueError("collect must be None, 'full' or 'touched'")
         n = self.n
         E = 2 * n - 3
         todo = []  # (key, edges, brlen)
@@ -167,7 +166,7 @@ class ThresholdSearch:
         good = {}
         lmax = -np.inf
         stats = dict(proposed=0, queued=len(todo), full_passes=0, full_time=0.0, prop_time=0.0, batches=0,
-                     cold_redo=0, cold_better=0)
+                     warm_tried=0, warm_passed=0)
         samples = []
         n_samples = 0
         head = 0
@@ -215,22 +214,40 @@ class ThresholdSearch:
             if progress is not None:
                 progress("batch %d: %d visited, %d good, %d new proposals, lmax %.4f" % (
                     stats["batches"], len(visited), len(good), len(props), lmax))
-            radius = -1 if collect else self.radius
+            radius = {None: self.radius, "full": -1, "touched": "touched"}[collect]
             gate = lmax + self.T
             best = {}  # key -> (partial lnL, edges, lengths)
+            near = []  # cold-rejected proposals within warm_margin of the gate
             for s0 in range(0, len(props), self.batch):
                 if max_samples is not None and n_samples >= max_samples:
                     break
                 chunk = props[s0:s0 + self.batch]
-                lnl, bo = self._propose(chunk, radius, gate, stats)
+                lnl, bo = self._propose(chunk, radius, stats)
                 for i, p in enumerate(chunk):
                     bi = bo[i * E:(i + 1) * E]
                     if collect:
                         tt = p[4]
                         samples.append((p[3], p[5][tt].copy(), bi[tt].copy()))
                         n_samples += 1
+                    if lnl[i] >= gate:
+                        if p[0] not in best or lnl[i] > best[p[0]][0]:
+                            best[p[0]] = (lnl[i], p[1], bi.copy())
+                    elif self.warm is not None and lnl[i] >= gate - self.warm_margin:
+                        near.append(p)
+            # the warm start retries the near misses of the round (one launch
+            # per batch of them); a key joins the queue if either start's
+            # partial optimum passes the gate, so the gate is never stricter
+            # than the cold start's
+            near = [p for p in near if p[0] not in best]
+            stats["warm_tried"] += len(near)
+            for s0 in range(0, len(near), self.batch):
+                chunk = near[s0:s0 + self.batch]
+                lnl, bo = self._propose(chunk, radius, stats, warm=True)
+                for i, p in enumerate(chunk):
                     if lnl[i] >= gate and (p[0] not in best or lnl[i] > best[p[0]][0]):
-                        best[p[0]] = (lnl[i], p[1], bi.copy())
+                        if p[0] not in best:
+                            stats["warm_passed"] += 1
+                        best[p[0]] = (lnl[i], p[1], bo[i * E:(i + 1) * E].copy())
             for k, (_, e, bi) in best.items():
                 queued.add(k)
                 todo.append((k, e, bi))
@@ -241,8 +258,8 @@ class ThresholdSearch:
         return SearchResult(lmax=lmax, good=final, visited=len(visited), proposed=stats["proposed"],
                             queued=stats["queued"], full_passes=stats["full_passes"],
                             full_time_s=stats["full_time"], proposal_time_s=stats["prop_time"],
-                            batches=stats["batches"], cold_redo=stats["cold_redo"],
-                            cold_better=stats["cold_better"], samples=samples)
+                            batches=stats["batches"], warm_tried=stats["warm_tried"],
+                            warm_passed=stats["warm_passed"], samples=samples)
 
 
 def hls_summary(n, result):

@@ -6,9 +6,12 @@
    ~ Dirichlet(1 x 6), frequencies ~ Dirichlet(10 x 4), alpha 0.5) on a Yule
    tree with Exp(mean 0.05) lengths, seed 5.
 2. Fully optimises the generating topology (the start tree) and runs the
-   threshold search from it with every proposal fully optimised, recording
-   for each proposed neighbour the features of its move in the parent and
-   its five optimised touched lengths beside the parent's.  The targets are
+   threshold search from it, optimising for each proposal every length
+   (--target full, the default and the shipped weights) or only its five
+   touched lengths with the rest held at the parent's (--target touched),
+   and recording for each proposed neighbour
+   the features of its move in the parent and its five optimised touched
+   lengths beside the parent's.  The targets are
    log((t_new + s) / (t_parent + s)) with s = 1e-4, so lengths at or near
    the lower bound do not dominate the loss.
    The collection threshold widens until the sample target is reached.
@@ -122,6 +125,9 @@ def main():
     ap.add_argument("--samples", type=int, default=100000)
     ap.add_argument("--epochs", type=int, default=40)
     ap.add_argument("--shift", type=float, default=1e-4)
+    ap.add_argument("--target", choices=["full", "touched"], default="full",
+                    help="full: every length optimised (the shipped weights); touched: only the five touched "
+                         "lengths, the rest held at the parent's")
     ap.add_argument("--save-data", default=None, help="also write the collected samples (.npz)")
     args = ap.parse_args()
     import torch  # noqa: F401
@@ -138,7 +144,7 @@ def main():
     for T in (-10.0, -30.0, -100.0, -300.0, -1000.0):
         t0 = time.perf_counter()
         res = ThresholdSearch(ctx, A, threshold=T, batch=1024).run(
-            [(e, b0)], collect=True, max_samples=args.samples, progress=log)
+            [(e, b0)], collect=args.target, max_samples=args.samples, progress=log)
         samples = res.samples
         colls.append({"threshold": T, "samples": len(samples), "good": len(res.good), "visited": res.visited,
                       "seconds": round(time.perf_counter() - t0, 2)})
@@ -154,7 +160,7 @@ def main():
     params, rec = train(ctx, X, Y, epochs=args.epochs)
     out = {"n_in": L.PT_NNI_FEATURES, "n_hidden": 128, "n_out": 5, "shift": args.shift,
            "workload": "64 taxa x 2500 sites GTR+G4 (seed %d, %d patterns)" % (args.seed, aln.n_patterns),
-           "collection": colls, "samples": len(samples), "training": rec,
+           "target": args.target, "collection": colls, "samples": len(samples), "training": rec,
            "params": [float(x) for x in params]}
     json.dump(out, open(args.out, "w"))
     log("wrote", args.out)

@@ -5,8 +5,10 @@ call only the oracle) and against the oracle run live.
 * Batching: all 512 topologies over four uneven alignments (27x1949,
   36x1812, 50x1133, 64x1008), optimised in one persistent launch in the
   shape the benchmark times (autotuned, replayed from a HIP graph), FP32 and
-  FP64; every optimum against the oracle's local maxima of that topology;
-  the likelihood at the starting lengths against the oracle's.
+  FP64; every optimum against the oracle's stored local maxima of that
+  topology, or, where the ascent found another, confirmed a local maximum by
+  the oracle's lnL, gradient and own ascent at the returned lengths; the
+  likelihood at the starting lengths against the oracle's.
 * Differentiation: lnL and all 97 branch-length derivatives of 256 trees of
   50 taxa x 1500 sites, FP32 and FP64, against the oracle gradient; the
   FP64 gradient against central differences of the oracle lnL on 8 trees.
@@ -106,22 +108,55 @@ def test_c3_batched_optimisation_all_512(ctx, c3):
     l64, b64, s64, _ = res[pt.PT_FP64]
     assert np.all(s32 == 0) and np.all(s64 == 0)
     assert np.all(l64 >= start - 1e-6 * np.abs(start))
-    # Every optimum must be one of the oracle's local maxima of that topology
-    # (several exist on some topologies; which one an ascent reaches depends
-    # on its path): the one the oracle reaches from the same start, or one it
-    # reaches from its two further starts.
+    # Several local maxima exist on some topologies, and which one an ascent
+    # reaches depends on its path: the library visits edges depth-first from
+    # leaf 0 and over-relaxes its steps from the second pass on, the oracle
+    # visits them by index.  An optimum is accepted when it is one of the
+    # oracle's stored local maxima of that topology (reached from the same
+    # start or from two further starts), or else when the oracle confirms it
+    # is one: its lnL at the returned lengths, its gradient there (every edge
+    # stationary, or at a bound with the derivative pointing out), and its
+    # own ascent started there, which must not move.
     optima = g["local_optima"]
     r64 = np.array([min(abs(l64[i] - x) / abs(x) for x in optima[i]) for i in range(len(optima))])
     a32 = np.array([min(abs(l32[i] - x) for x in optima[i]) for i in range(len(optima))])
     same64 = np.abs(l64 - want) / np.abs(want) < FP64_REL
     same32 = np.abs(l32 - want) < FP32_ABS
-    say("C3 optima vs oracle: fp64 max rel", r64.max(), "fp32 max abs", a32.max(),
-        "worst fp32 topology", int(np.argmax(a32)))
     say("C3 topologies at the oracle's same-start optimum: fp64 %d, fp32 %d of %d; elsewhere (fp64):"
         % (same64.sum(), same32.sum(), len(want)),
         [(i, round(float(l64[i] - want[i]), 4)) for i in np.nonzero(~same64)[0]])
-    assert r64.max() < FP64_REL
-    assert a32.max() < FP32_ABS
+    other64 = np.nonzero(r64 >= FP64_REL)[0]
+    other32 = np.nonzero(a32 >= FP32_ABS)[0]
+    say("C3 optima not among the oracle's stored maxima: fp64", list(other64), "fp32", list(other32))
+    # a handful of topologies at most; each is checked with the oracle below
+    assert len(other64) <= 16 and len(other32) <= 16
+    off = T.edge_offset
+    data = [oc.Data.from_alignment(a) for a in alns]
+
+    def oracle_confirms(i, b, lnl, lnl_tol, gain_tol):
+        D = data[idx[i]]
+        bi = b[off[i]:off[i + 1]]
+        l0, gr, hd = oc.gradient(D, trees[i], bi)
+        assert abs(l0 - lnl) <= lnl_tol, (i, l0, lnl)
+        lo = bi <= oc.T_MIN * (1 + 1e-9)
+        hi = bi >= oc.T_MAX * (1 - 1e-9)
+        # predicted gain of a Newton step on each edge (0 where the
+        # derivative points out of a bound)
+        pred = np.where(hd < 0, gr * gr / (2 * np.maximum(-hd, 1e-300)), np.inf)
+        pred[(lo & (gr <= 0)) | (hi & (gr >= 0))] = 0.0
+        lo_opt, _, _, _ = oc.optimize(D, trees[i], bi)
+        say("  topology %d: oracle lnL %.6f, largest predicted edge gain %.3g, oracle ascent from there gains %.3g"
+            % (i, l0, pred.max(), lo_opt - l0))
+        assert pred.max() < gain_tol, (i, pred.max())
+        assert lo_opt - l0 < gain_tol, (i, lo_opt - l0)
+
+    for i in other64:
+        oracle_confirms(i, b64, l64[i], 1e-11 * abs(l64[i]), 1e-6)
+    for i in other32:
+        oracle_confirms(i, b32, l32[i], FP32_ABS, 1e-3)
+    same_as_stored = r64 < FP64_REL
+    say("C3 optima vs the oracle's stored maxima, where the same: fp64 max rel",
+        r64[same_as_stored].max(), "fp32 max abs", a32[a32 < FP32_ABS].max())
     # the reported lnL is the lnL at the reported lengths
     at = pt.pt_batch_loglik(ctx, A, T, b64, pt.PT_FP64)
     assert np.max(np.abs(at - l64) / np.abs(l64)) < 1e-12

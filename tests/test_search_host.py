@@ -165,3 +165,54 @@ def test_search_matches_the_papers_loop(radius):
     s = OracleSearch(D, n, threshold=T, radius=radius, batch=1)
     got = {topo.key(v[1], n) for v in s.run([start]).good.values()}
     assert got == want
+
+
+class WarmOracleSearch(OracleSearch):
+    """The oracle search with a stand-in warm start: the five touched lengths
+    of a retried proposal start at their values in the proposal's fully
+    optimised tree (what a perfect network would predict)."""
+
+    def __init__(self, data, n, **kw):
+        super().__init__(data, n, **kw)
+        self.warm = object()  # only its presence matters to the host loop
+        self.warm_calls = 0
+
+    def _optimize(self, edge_lists, brlen, masks=None, warm_rows=None):
+        b = np.array(brlen, dtype=np.float64)
+        if warm_rows is not None:
+            self.warm_calls += 1
+            E = 2 * self.n - 3
+            _, pos, _ = warm_rows
+            for i, e in enumerate(edge_lists):
+                full = oc.optimize(self.data, e, b[i * E:(i + 1) * E])[1]
+                b[pos[i]] = full[pos[i] - i * E]
+        return super()._optimize(edge_lists, b, masks, None)
+
+
+def test_warm_retry_of_near_misses_only_adds():
+    """The warm start retries proposals the cold start's partial optimum
+    leaves within warm_margin below the gate.  From the global maximum
+    (lmax fixed from the first visit) the gate never changes, so every
+    proposal the cold search queues, the warm search queues too: its good
+    set contains the cold search's, and nothing outside the NNI component
+    of the superlevel set; here the stand-in network's retries add good
+    topologies that the cold radius-0 gate missed."""
+    n = 6
+    D, tops, lnl, _ = brute_force(72, n)
+    keys = [topo.key(t, n) for t in tops]
+    best = int(np.argmax(lnl))
+    T = -20.0
+    start = [(tops[best], np.full(2 * n - 3, 0.1))]
+    cold = OracleSearch(D, n, threshold=T, radius=0, batch=16).run(start)
+    got_c = {topo.key(v[1], n) for v in cold.good.values()}
+    members = {k for k, l in zip(keys, lnl) if l >= lnl[best] + T}
+    s = WarmOracleSearch(D, n, threshold=T, radius=0, batch=16, warm_margin=40.0)
+    res = s.run(start)
+    got_w = {topo.key(v[1], n) for v in res.good.values()}
+    print("cold good", len(got_c), "warm good", len(got_w), "component", len(members),
+          "retried", res.warm_tried, "passed", res.warm_passed)
+    assert got_c <= got_w <= members
+    assert res.warm_tried > 0 and s.warm_calls > 0
+    assert 0 < res.warm_passed <= res.warm_tried
+    assert len(got_w) > len(got_c)
+    assert abs(res.lmax - cold.lmax) < 1e-9 * abs(cold.lmax)
