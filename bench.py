@@ -131,6 +131,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-extras", action="store_true", help="only the headline measurement")
+    ap.add_argument("--no-search", action="store_true", help="skip the threshold-search extra (profiling runs)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first run an elementwise copy of 256 MiB (y = -x, float32) whose known traffic "
                          "calibrates hardware byte counters")
@@ -419,38 +420,39 @@ def main():
                          "frac": round(flops3r / (ms3r / 1e3) / 1e12 / FP64_VALU_PEAK_TFLOPS, 4),
                          "flops_per_call": flops3r, "bytes_per_call": by3r},
             "note": "graph of k_pmat + k_loglik_reg + k_reduce"}
-        log("threshold search, cold and warm-started ...")
-        # the learned warm start in the threshold search (T = -10, radius-0
-        # proposals, batch 1024, FP32 partials) on the network's held-out
-        # 64-taxon x 2500-site alignment (seed 6): the cold start gates every
-        # proposal, the network's lengths retry the near misses
-        from paper_1811_11007_amd import search as S
-        from paper_1811_11007_amd.train_warmstart import optimise_start, workload
-        e5, b5, aln5 = workload(6)
-        A5 = pt.Alignment.from_synth(ctx, aln5)
-        b5o, _ = optimise_start(ctx, A5, e5, b5)
-        warm = S.WarmStart.load(ctx, os.path.join(ROOT, "paper_1811_11007_amd", "warmstart_64x2500.json"))
-        runs = {}
-        for name, w in (("cold", None), ("warm", warm), ("cold_again", None)):
-            t0 = time.perf_counter()
-            res = S.ThresholdSearch(ctx, A5, threshold=-10.0, radius=0, warm=w, batch=1024).run([(e5, b5o)])
-            runs[name] = (time.perf_counter() - t0, res)
-        rc, rw = runs["cold_again"][1], runs["warm"][1]
-        out["search"] = {
-            "workload": "threshold search T=-10, radius-0 proposals, batch 1024, FP32 partials, held-out "
-                        "64 taxa x 2500 sites (seed 6), from the optimised generating tree",
-            "cold": {"seconds": round(runs["cold_again"][0], 3), "good": len(rc.good), "visited": rc.visited,
-                     "proposed": rc.proposed, "full_passes": rc.full_passes,
-                     "proposal_seconds": round(rc.proposal_time_s, 3), "visit_seconds": round(rc.full_time_s, 3)},
-            "warm": {"seconds": round(runs["warm"][0], 3), "good": len(rw.good), "visited": rw.visited,
-                     "proposed": rw.proposed, "full_passes": rw.full_passes,
-                     "proposal_seconds": round(rw.proposal_time_s, 3), "visit_seconds": round(rw.full_time_s, 3),
-                     "near_misses_retried": rw.warm_tried, "retries_passed": rw.warm_passed},
-            "warm_contains_cold": set(rc.good) <= set(rw.good),
-            "good_only_warm": len(set(rw.good) - set(rc.good)),
-            "good_only_cold": len(set(rc.good) - set(rw.good)),
-            "warm_over_cold_time": round(runs["warm"][0] / runs["cold_again"][0], 3),
-            "note": "the first cold run warms up plan memory and is not reported"}
+        if not args.no_search:
+            log("threshold search, cold and warm-started ...")
+            # the learned warm start in the threshold search (T = -10, radius-0
+            # proposals, batch 1024, FP32 partials) on the network's held-out
+            # 64-taxon x 2500-site alignment (seed 6): the cold start gates every
+            # proposal, the network's lengths retry the near misses
+            from paper_1811_11007_amd import search as S
+            from paper_1811_11007_amd.train_warmstart import optimise_start, workload
+            e5, b5, aln5 = workload(6)
+            A5 = pt.Alignment.from_synth(ctx, aln5)
+            b5o, _ = optimise_start(ctx, A5, e5, b5)
+            warm = S.WarmStart.load(ctx, os.path.join(ROOT, "paper_1811_11007_amd", "warmstart_64x2500.json"))
+            runs = {}
+            for name, w in (("cold", None), ("warm", warm), ("cold_again", None)):
+                t0 = time.perf_counter()
+                res = S.ThresholdSearch(ctx, A5, threshold=-10.0, radius=0, warm=w, batch=1024).run([(e5, b5o)])
+                runs[name] = (time.perf_counter() - t0, res)
+            rc, rw = runs["cold_again"][1], runs["warm"][1]
+            out["search"] = {
+                "workload": "threshold search T=-10, radius-0 proposals, batch 1024, FP32 partials, held-out "
+                            "64 taxa x 2500 sites (seed 6), from the optimised generating tree",
+                "cold": {"seconds": round(runs["cold_again"][0], 3), "good": len(rc.good), "visited": rc.visited,
+                         "proposed": rc.proposed, "full_passes": rc.full_passes,
+                         "proposal_seconds": round(rc.proposal_time_s, 3), "visit_seconds": round(rc.full_time_s, 3)},
+                "warm": {"seconds": round(runs["warm"][0], 3), "good": len(rw.good), "visited": rw.visited,
+                         "proposed": rw.proposed, "full_passes": rw.full_passes,
+                         "proposal_seconds": round(rw.proposal_time_s, 3), "visit_seconds": round(rw.full_time_s, 3),
+                         "near_misses_retried": rw.warm_tried, "retries_passed": rw.warm_passed},
+                "warm_contains_cold": set(rc.good) <= set(rw.good),
+                "good_only_warm": len(set(rw.good) - set(rc.good)),
+                "good_only_cold": len(set(rc.good) - set(rw.good)),
+                "warm_over_cold_time": round(runs["warm"][0] / runs["cold_again"][0], 3),
+                "note": "the first cold run warms up plan memory and is not reported"}
         log("copy bandwidth ...")
         xc = torch.empty(1 << 28, dtype=torch.float32, device=dev)  # 1 GiB
         yc = torch.empty_like(xc)
@@ -471,10 +473,17 @@ def main():
         del xc, yc
         if os.path.exists(TRAFFIC):
             tr = json.load(open(TRAFFIC))
-            if tr.get("kernel_hash") == kernel_hash() and "tiles_512_fp32" in tr:
-                # measured FETCH_SIZE + WRITE_SIZE bytes of the tile kernel over
-                # the whole graph's time (a lower bound for the kernel alone)
-                out["pruning"]["counter_GBs"] = round(tr["tiles_512_fp32"]["bytes_per_launch"] / (ms3 / 1e3) / 1e9, 1)
+            if tr.get("kernel_hash") == kernel_hash():
+                # measured FETCH_SIZE + WRITE_SIZE bytes per launch of each
+                # path's main kernel (scaled by the copy probe's counts), over
+                # the whole call's time (a lower bound for the kernel alone)
+                def counter(key, ms):
+                    return round(tr[key]["bytes_per_launch"] / (ms / 1e3) / 1e9, 1) if key in tr else None
+                out["pruning"]["counter_GBs"] = counter("tiles_512_fp32", ms3)
+                out["pruning"]["fp64"]["counter_GBs"] = counter("tiles_512_fp64", ms3d)
+                out["loglik_registers"]["roofline"]["traffic"] = tr.get("loglik_reg_512", {}).get("bytes_per_launch")
+                out["batched_512"]["counter_GBs"] = counter("optimize_512_fp32", ms3o)
+                out["gradient"]["counter_GBs"] = counter("grad_256_fp32", ms4)
 
     if not args.no_cpu:
         log("oracle cpu baseline ...")
