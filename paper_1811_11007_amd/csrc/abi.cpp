@@ -1604,16 +1604,17 @@ struct pt_mlp {
     float *d_p = nullptr, *d_m = nullptr, *d_v = nullptr, *d_g = nullptr;
     int cap = 0;
     float *d_h = nullptr, *d_y = nullptr, *d_dy = nullptr, *d_dz = nullptr;
-    double *d_rl = nullptr;
+    double *d_rl = nullptr, *d_part = nullptr;  // d_part: row-tile sums of the weight gradient
 };
 
 namespace {
 
 void mlp_free_scratch(pt_mlp *m) {
-    for (void *p : {(void *)m->d_h, (void *)m->d_y, (void *)m->d_dy, (void *)m->d_dz, (void *)m->d_rl})
+    for (void *p : {(void *)m->d_h, (void *)m->d_y, (void *)m->d_dy, (void *)m->d_dz, (void *)m->d_rl,
+                    (void *)m->d_part})
         if (p) (void)hipFree(p);
     m->d_h = m->d_y = m->d_dy = m->d_dz = nullptr;
-    m->d_rl = nullptr;
+    m->d_rl = m->d_part = nullptr;
     m->cap = 0;
 }
 
@@ -1626,6 +1627,8 @@ pt_status mlp_scratch(pt_mlp *m, int rows) {
     PT_HIP(hipMalloc(&m->d_y, sizeof(float) * r * m->no));
     PT_HIP(hipMalloc(&m->d_dy, sizeof(float) * r * m->no));
     PT_HIP(hipMalloc(&m->d_rl, sizeof(double) * r));
+    const size_t part = pt::mlp_wgrad_part_doubles(rows, m->ni, m->nh, m->no);
+    if (part) PT_HIP(hipMalloc(&m->d_part, sizeof(double) * part));
     m->cap = rows;
     return PT_OK;
 }
@@ -1713,7 +1716,7 @@ pt_status pt_mlp_gradient(pt_mlp *mlp, const float *d_x, const float *d_target, 
     PT_HIP(pt::mlp_forward(d_x, mlp->d_p, rows, mlp->ni, mlp->nh, mlp->no, mlp->d_h, mlp->d_y, s));
     PT_HIP(pt::mlp_loss_grad(mlp->d_y, d_target, rows, mlp->no, mlp->d_dy, mlp->d_rl, d_loss, s));
     PT_HIP(pt::mlp_backward(d_x, mlp->d_p, mlp->d_h, mlp->d_dy, rows, mlp->ni, mlp->nh, mlp->no, mlp->d_dz, d_grad,
-                            s));
+                            mlp->d_part, s));
     return PT_OK;
 }
 

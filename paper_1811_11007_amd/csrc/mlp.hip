@@ -6,11 +6,15 @@
 //
 // Parameters live in one FP32 array packed as W1, b1, W2, b2 (row-major).
 // Training minimises the mean over rows and outputs of (y - target)^2 with
-// Adam.  Weight gradients are sums over rows; each is formed by one block in
-// a fixed order (per-thread strided partial sums in FP64, then a fixed tree),
-// so training is deterministic.  Matrices are small (n_in ~ 16, n_hidden
-// 128, n_out 5): the work is one thread per output element with the weights
-// read through the cache, and per-row activations kept for the backward pass.
+// Adam.  Weight gradients are sums over rows, formed in a fixed order, so
+// training is deterministic: blocks of 32 rows staged in LDS, each block's
+// sums in FP64 and the blocks added in order (a network whose
+// staging exceeds 48 KiB of LDS: one block per parameter, per-thread strided
+// partial sums in FP64, then a fixed tree).  Matrices are small (n_in ~ 16,
+// n_hidden 128, n_out 5): the hidden layer is one thread per element with
+// the weights read through the cache; the output layer stages 64 rows of
+// activations and the weights in LDS; per-row activations are kept for the
+// backward pass.
 #include <hip/hip_runtime.h>
 
 #include "mlp.hpp"
@@ -36,6 +40,33 @@ __global__ void k_mlp_out(const float *hact, const float *p, int rows, int ni, i
     float s = b2[o];
     for (int h = 0; h < nh; ++h) s += hact[(size_t)r * nh + h] * W2[(size_t)h * no + o];
     y[g] = s;
+}
+
+// The output layer by row tiles: a block stages 64 rows of h and all of W2
+// and b2 in LDS (coalesced), then each thread forms outputs from LDS; the
+// same sums in the same order as k_mlp_out.
+constexpr int kOutRows = 64;
+
+__global__ void __launch_bounds__(256) k_mlp_out_tiles(const float *hact, const float *p, int rows, int ni, int nh,
+                                                        int no, float *y) {
+    extern __shared__ float tile[];
+    // rows padded by one word, so the lanes of a wave (several rows) read
+    // different LDS banks
+    const int ld = nh + 1;
+    float *th = tile, *tw = th + kOutRows * ld, *tb = tw + (size_t)nh * no;
+    const float *W2 = p + (size_t)ni * nh + nh, *b2 = W2 + (size_t)nh * no;
+    const int r0 = blockIdx.x * kOutRows;
+    const int nr = min(kOutRows, rows - r0);
+    for (int i = threadIdx.x; i < nr * nh; i += 256) th[(i / nh) * ld + i % nh] = hact[(size_t)r0 * nh + i];
+    for (int i = threadIdx.x; i < nh * no; i += 256) tw[i] = W2[i];
+    for (int i = threadIdx.x; i < no; i += 256) tb[i] = b2[i];
+    __syncthreads();
+    for (int g = threadIdx.x; g < nr * no; g += 256) {
+        const int r = g / no, o = g % no;
+        float s = tb[o];
+        for (int h = 0; h < nh; ++h) s += th[r * ld + h] * tw[h * no + o];
+        y[(size_t)r0 * no + g] = s;
+    }
 }
 
 // dY = 2 (y - target) / (rows * no); loss partial sums per row.
@@ -113,6 +144,72 @@ __global__ void __launch_bounds__(256) k_mlp_wgrad(const float *x, const float *
     if (threadIdx.x == 0) grad[q] = (float)s;
 }
 
+// Weight gradients by row tiles: block b sums the terms of its 32 rows for
+// every parameter, from their rows of x, h, dz and dy staged in LDS
+// (instead of one block per parameter re-reading every row), and
+// writes them to part[b][np] in FP64; k_mlp_wgrad_sum then adds the blocks
+// in order.  Each sum runs over the rows in order; a thread accumulates its
+// parameters across the stagings in its own entries of part.
+constexpr int kWgradRows = 32;  // rows staged in LDS at a time
+constexpr int kWgradSub = 1;    // stagings per block
+
+__global__ void __launch_bounds__(256) k_mlp_wgrad_tiles(const float *x, const float *hact, const float *dz,
+                                                          const float *dy, int rows, int ni, int nh, int no,
+                                                          double *part) {
+    extern __shared__ float tile[];
+    float *tx = tile, *th = tx + kWgradRows * ni, *tz = th + kWgradRows * nh, *ty = tz + kWgradRows * nh;
+    const int n_w1 = ni * nh, n_b1 = nh, n_w2 = nh * no;
+    const int np = n_w1 + n_b1 + n_w2 + no;
+    for (int sub = 0; sub < kWgradSub; ++sub) {
+        const int r0 = (blockIdx.x * kWgradSub + sub) * kWgradRows;
+        if (r0 >= rows) break;  // uniform
+        const int nr = min(kWgradRows, rows - r0);
+        if (sub > 0) __syncthreads();  // the previous staging is read
+        for (int i = threadIdx.x; i < nr * ni; i += 256) tx[i] = x[(size_t)r0 * ni + i];
+        for (int i = threadIdx.x; i < nr * nh; i += 256) {
+            th[i] = hact[(size_t)r0 * nh + i];
+            tz[i] = dz[(size_t)r0 * nh + i];
+        }
+        for (int i = threadIdx.x; i < nr * no; i += 256) ty[i] = dy[(size_t)r0 * no + i];
+        __syncthreads();
+        for (int q = threadIdx.x; q < np; q += 256) {
+            double s = 0.0;
+            if (q < n_w1) {
+                const int f = q / nh, h = q % nh;
+                for (int r = 0; r < nr; ++r) s += (double)tx[r * ni + f] * (double)tz[r * nh + h];
+            } else if (q < n_w1 + n_b1) {
+                const int h = q - n_w1;
+                for (int r = 0; r < nr; ++r) s += (double)tz[r * nh + h];
+            } else if (q < n_w1 + n_b1 + n_w2) {
+                const int k = q - n_w1 - n_b1, h = k / no, o = k % no;
+                for (int r = 0; r < nr; ++r) s += (double)th[r * nh + h] * (double)ty[r * no + o];
+            } else {
+                const int o = q - n_w1 - n_b1 - n_w2;
+                for (int r = 0; r < nr; ++r) s += (double)ty[r * no + o];
+            }
+            // the block's sum over its stagings, in order
+            double *out = part + (size_t)blockIdx.x * np + q;
+            *out = sub == 0 ? s : *out + s;
+        }
+    }
+}
+
+__global__ void k_mlp_wgrad_sum(const double *part, int tiles, int np, float *grad) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= np) return;
+    double s = 0.0;
+    int b = 0;
+    for (; b + 8 <= tiles; b += 8) {  // eight loads in flight, added in order
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = part[(size_t)(b + u) * np + q];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s += v[u];
+    }
+    for (; b < tiles; ++b) s += part[(size_t)b * np + q];
+    grad[q] = (float)s;
+}
+
 __global__ void k_adam(float *p, const float *g, float *m, float *v, int n, float lr, float b1, float b2, float eps,
                        float c1, float c2) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -154,17 +251,40 @@ hipError_t mlp_forward(const float *x, const float *p, int rows, int ni, int nh,
                        hipStream_t s) {
     if (rows <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_mlp_hidden, dim3(blocks((int64_t)rows * nh, 256)), dim3(256), 0, s, x, p, rows, ni, nh, hact);
-    hipLaunchKernelGGL(k_mlp_out, dim3(blocks((int64_t)rows * no, 256)), dim3(256), 0, s, hact, p, rows, ni, nh, no, y);
+    const size_t lds = sizeof(float) * ((size_t)kOutRows * (nh + 1) + (size_t)nh * no + no);
+    if (lds <= kMlpTileLdsMax)
+        hipLaunchKernelGGL(k_mlp_out_tiles, dim3(blocks(rows, kOutRows)), dim3(256), lds, s, hact, p, rows, ni, nh, no,
+                           y);
+    else
+        hipLaunchKernelGGL(k_mlp_out, dim3(blocks((int64_t)rows * no, 256)), dim3(256), 0, s, hact, p, rows, ni, nh, no,
+                           y);
     return hipGetLastError();
 }
 
+size_t mlp_wgrad_tile_lds(int ni, int nh, int no) {
+    return sizeof(float) * kWgradRows * ((size_t)ni + 2 * (size_t)nh + (size_t)no);
+}
+
+size_t mlp_wgrad_part_doubles(int rows, int ni, int nh, int no) {
+    if (mlp_wgrad_tile_lds(ni, nh, no) > kMlpTileLdsMax) return 0;
+    const int tiles = (rows + kWgradRows * kWgradSub - 1) / (kWgradRows * kWgradSub);
+    return (size_t)tiles * ((size_t)ni * nh + nh + (size_t)nh * no + no);
+}
+
 hipError_t mlp_backward(const float *x, const float *p, const float *hact, const float *dy, int rows, int ni, int nh,
-                        int no, float *dz, float *grad, hipStream_t s) {
+                        int no, float *dz, float *grad, double *part, hipStream_t s) {
     if (rows <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_mlp_dz, dim3(blocks((int64_t)rows * nh, 256)), dim3(256), 0, s, dy, hact, p, rows, ni, nh,
                        no, dz);
     const int np = ni * nh + nh + nh * no + no;
-    hipLaunchKernelGGL(k_mlp_wgrad, dim3(np), dim3(256), 0, s, x, hact, dz, dy, rows, ni, nh, no, grad);
+    const size_t lds = mlp_wgrad_tile_lds(ni, nh, no);
+    if (part && lds <= kMlpTileLdsMax) {
+        const int tiles = (rows + kWgradRows * kWgradSub - 1) / (kWgradRows * kWgradSub);
+        hipLaunchKernelGGL(k_mlp_wgrad_tiles, dim3(tiles), dim3(256), lds, s, x, hact, dz, dy, rows, ni, nh, no, part);
+        hipLaunchKernelGGL(k_mlp_wgrad_sum, dim3(blocks(np, 64)), dim3(64), 0, s, part, tiles, np, grad);
+    } else {
+        hipLaunchKernelGGL(k_mlp_wgrad, dim3(np), dim3(256), 0, s, x, hact, dz, dy, rows, ni, nh, no, grad);
+    }
     return hipGetLastError();
 }
 
