@@ -29,6 +29,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 GOLDEN = os.path.join(ROOT, "tests", "golden", "c2_hillclimb.json")
 GOLDEN3 = os.path.join(ROOT, "tests", "golden", "c3_batch512.json")
+GOLDEN4 = os.path.join(ROOT, "tests", "golden", "c4_grad256.json")
 TRAFFIC = os.path.join(ROOT, "profiles", "traffic_counters.json")
 FP64_VALU_PEAK_TFLOPS = 78.6
 
@@ -297,9 +298,13 @@ def main():
         b3 = torch.tensor(lens3, dtype=torch.float64, device=dev)
         reps = 20
 
+        tiles3 = {}
+
         def time_loglik(precision, path):
             plan = pt.Plan(ctx, A3, T3, pt.PT_PLAN_LOGLIK, precision)
             plan.set_loglik_path(path)
+            if path == pt.PT_LOGLIK_STORED:
+                tiles3[precision] = plan.autotune_tiles(b3)
             l = torch.zeros(T3.n_trees, dtype=torch.float64, device=dev)
             with torch.cuda.stream(stream):
                 plan.set_graphs(True)
@@ -375,6 +380,7 @@ def main():
         b4 = torch.tensor(lens4.ravel(), dtype=torch.float64, device=dev)
         l4 = torch.zeros(T4.n_trees, dtype=torch.float64, device=dev)
         g4 = torch.zeros_like(b4)
+        tiles4 = plan4.autotune_tiles(b4)
         with torch.cuda.stream(stream):
             plan4.set_graphs(True)
             for _ in range(3):
@@ -392,7 +398,13 @@ def main():
                                        "derivative per edge)",
                            "ms_per_call": round(ms4, 4), "trees_per_s": round(T4.n_trees / (ms4 / 1e3), 1),
                            "algorithmic_bytes": by4, "achieved_GBs": round(by4 / (ms4 / 1e3) / 1e9, 1),
-                           "frac_of_peak": round(by4 / (ms4 / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
+                           "frac_of_peak": round(by4 / (ms4 / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                           "patterns_per_tile": tiles4}
+        # the stored oracle gradients of the same trees (tests/golden/c4_grad256.json)
+        g4_want = np.asarray(json.load(open(GOLDEN4))["grad"]).ravel()
+        e4 = float(np.max(np.abs(g4.cpu().numpy() - g4_want) / np.maximum(1.0, np.abs(g4_want))))
+        out["gradient"]["max_err_vs_oracle"] = e4
+        out["gradient"]["all_within_1e-3"] = e4 < 1e-3
         plan4.close()
         out["pruning"] = {"workload": "512 topologies over 27x1949, 36x1812, 50x1133, 64x1008 GTR+G4, FP32 "
                                       "partials stored in HBM (the post-order pass that starts an optimisation "
@@ -403,10 +415,12 @@ def main():
                           "counter_GBs": None,
                           "max_abs_dlnl_vs_oracle": float(np.max(np.abs(l3 - start3))),
                           "note": "graph of k_pmat + k_tiles + k_reduce",
+                          "patterns_per_tile": tiles3.get(pt.PT_FP32),
                           "fp64": {"ms_per_call": round(ms3d, 4), "algorithmic_bytes": by3d,
                                    "achieved_GBs": round(by3d / (ms3d / 1e3) / 1e9, 1),
                                    "frac_of_peak": round(by3d / (ms3d / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
                                    "max_rel_dlnl_vs_oracle": float(np.max(np.abs(l3d - start3) / np.abs(start3))),
+                                   "patterns_per_tile": tiles3.get(pt.PT_FP64),
                                    "max_abs_dlnl_vs_fp32": d3}}
         d3r = np.abs(l3r - start3)
         out["loglik_registers"] = {

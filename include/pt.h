@@ -225,6 +225,21 @@ pt_status pt_plan_optimize(pt_plan *plan, double *d_brlen_inout, const pt_opt *o
 pt_status pt_plan_grad(pt_plan *plan, const double *d_brlen, double *d_lnl,
                        double *d_grad, double *d_hess, void *stream);
 
+/* Patterns per tile of the stored post-order pass and the gradient (64, 128
+ * or 256 = one block of that many threads, one pattern each; 256 by
+ * default): more, smaller tiles give a small batch more blocks to spread
+ * over the device, larger ones fewer passes over each tree's matrices.
+ * Re-tiling synchronises the device and drops the plan's captured graphs;
+ * results are the same up to the order of the per-tile sums.  EINVAL for
+ * another count.  pt_plan_autotune_tiles times the plan's gradient (or, with
+ * no gradient, its stored likelihood pass) at each count, from the lengths
+ * d_brlen, keeps the fastest for the plan and for later plans of the same
+ * precision, padded categories and largest pattern and edge counts in this
+ * context, and writes it to *patterns_out (NULL ok). */
+pt_status pt_plan_set_tile_patterns(pt_plan *plan, int32_t patterns);
+pt_status pt_plan_tile_patterns(const pt_plan *plan, int32_t *patterns);
+pt_status pt_plan_autotune_tiles(pt_plan *plan, const double *d_brlen, int32_t *patterns_out);
+
 /* Which pass computes lnL on a PT_PLAN_LOGLIK plan.
  * PT_LOGLIK_REGISTERS (the default whenever every tree fits it): Felsenstein
  * pruning with no partial stored in device memory -- each pattern and

@@ -27,6 +27,7 @@ EXPORTS = [
     "pt_plan_create", "pt_plan_destroy", "pt_plan_set_graphs", "pt_plan_loglik",
     "pt_plan_optimize", "pt_plan_set_alpha", "pt_plan_optimize_alpha", "pt_plan_grad", "pt_plan_autotune",
     "pt_plan_traffic", "pt_plan_set_profile", "pt_plan_set_loglik_path", "pt_plan_info", "pt_plan_set_launch", "pt_plan_launch_shape",
+    "pt_plan_set_tile_patterns", "pt_plan_tile_patterns", "pt_plan_autotune_tiles",
     "pt_model_info", "pt_tree_check", "pt_nni_neighbors", "pt_topology_key", "pt_topology_keys",
     "pt_nni_features", "pt_radius_masks", "pt_split_frequencies", "pt_majority_consensus",
     "pt_mlp_create", "pt_mlp_destroy", "pt_mlp_param_count", "pt_mlp_get_params", "pt_mlp_set_params",
@@ -106,6 +107,9 @@ def lib():
         L.pt_plan_loglik.argtypes = [vp, vp, vp, vp]
         L.pt_plan_optimize.argtypes = [vp, vp, P(pt_opt), vp, vp, vp, vp]
         L.pt_plan_set_alpha.argtypes = [vp, vp, vp]
+        L.pt_plan_set_tile_patterns.argtypes = [vp, i32]
+        L.pt_plan_tile_patterns.argtypes = [vp, P(i32)]
+        L.pt_plan_autotune_tiles.argtypes = [vp, vp, P(i32)]
         L.pt_plan_set_launch.argtypes = [vp, i32, i32]
         L.pt_plan_launch_shape.argtypes = [vp, P(i32), P(i32), P(i32)]
         L.pt_plan_optimize_alpha.argtypes = [vp, vp, P(pt_opt), vp, ctypes.c_double, ctypes.c_double,
@@ -510,6 +514,21 @@ class Plan:
     def set_launch(self, block, groups=1):
         """Optimisation kernel shape: threads per block, blocks per tree."""
         check(lib().pt_plan_set_launch(self.h, int(block), int(groups)))
+
+    def autotune_tiles(self, d_brlen):
+        """Patterns per tile of the stored pass and gradient: the fastest of
+        64, 128 and 256 on this plan (see pt.h)."""
+        n = ctypes.c_int32()
+        check(lib().pt_plan_autotune_tiles(self.h, ctypes.c_void_p(d_brlen.data_ptr()), ctypes.byref(n)))
+        return n.value
+
+    def set_tile_patterns(self, patterns):
+        check(lib().pt_plan_set_tile_patterns(self.h, int(patterns)))
+
+    def tile_patterns(self):
+        n = ctypes.c_int32()
+        check(lib().pt_plan_tile_patterns(self.h, ctypes.byref(n)))
+        return n.value
 
     def set_loglik_path(self, path):
         """PT_LOGLIK_REGISTERS (default) or PT_LOGLIK_STORED; see pt.h."""

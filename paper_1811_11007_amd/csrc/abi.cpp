@@ -78,6 +78,9 @@ struct pt_ctx {
     // tuned (threads per block, blocks per tree) of the optimisation kernel,
     // per (precision, padded categories, largest pattern count)
     std::map<std::tuple<int, int, int>, std::pair<int, int>> tuned;
+    // tuned patterns per tile of the stored pass and gradient, per
+    // (precision, padded categories, largest pattern count, largest edge count)
+    std::map<std::tuple<int, int, int, int>, int> tuned_tiles;
     // device memory of destroyed plans: a search creates a plan of the same
     // size for every batch, and a fresh hipMalloc / hipFree of tens of GB
     // each time cost far more than the optimisation itself
@@ -101,6 +104,8 @@ struct pt_plan {
     int n_trees = 0;
     int64_t n_edges = 0;
     int max_P = 0, max_E = 0, n_tiles = 0, kp = 1;
+    int tile_pats = pt::kTileBlock;      // patterns per tile of the stored pass and gradient
+    size_t tile_cap = 0, part_cap = 0;   // allocated entries of d_tile_tree and d_part
     std::vector<int> tree_E;
     AlnDev *d_alns = nullptr;
     Op *d_ops = nullptr;
@@ -281,7 +286,7 @@ int64_t tree_bytes(int n, const AlnDev &a, int precision, int kinds) {
     int64_t b = (int64_t)slots * items * 4 * store_bytes(precision) + (int64_t)slots * a.P * 2;
     b += (int64_t)E * a.Kp * 16 * 8 + 64 * E + 256;
     if (kinds & (PT_PLAN_LOGLIK | PT_PLAN_GRAD)) {
-        int64_t tiles = (a.P + pt::kTileBlock * pt::kTileItems - 1) / (pt::kTileBlock * pt::kTileItems);
+        int64_t tiles = (a.P + 63) / 64;  // the smallest tile (pt_plan_set_tile_patterns)
         b += tiles * (int64_t)E * 3 * 8 + tiles * 4;
     }
     return b;
@@ -359,6 +364,61 @@ pt_status configure_shape(pt_plan *pl, int block, int groups = 1) {
     pl->opt_tab_lds = lds_ok;
     pl->lds_opt = lds;
     pl->opt_grid = grid;
+    return PT_OK;
+}
+
+// Re-tiles the stored pass and the gradient at `pats` patterns per tile:
+// each tree's tile count, the tiles of the longest programs first (as at
+// build time), the tile-to-tree map and the per-tile sums, reallocated when
+// they grow.  Captured graphs are dropped.
+pt_status set_tile_pats(pt_plan *pl, int pats) {
+    if (!pt::tile_patterns_supported(pats)) return fail(PT_EINVAL, "patterns per tile must be 64, 128 or 256");
+    if (!(pl->kinds & (PT_PLAN_LOGLIK | PT_PLAN_GRAD)) || pl->n_trees == 0) {
+        pl->tile_pats = pats;
+        return PT_OK;
+    }
+    const int B = pl->n_trees;
+    std::vector<int> order(B);
+    for (int b = 0; b < B; ++b) order[b] = b;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return pl->tree_E[x] > pl->tree_E[y]; });
+    std::vector<int32_t> tile_tree;
+    std::vector<TreeDev> tll = pl->tll_h, tgr = pl->tgr_h;
+    int tiles = 0;
+    for (int b : order) {
+        const int nt = (pl->alns_h[b].P + pats - 1) / pats;
+        tll[b].n_tiles = tgr[b].n_tiles = nt;
+        tll[b].tile_begin = tgr[b].tile_begin = tiles;
+        for (int x = 0; x < nt; ++x) tile_tree.push_back(b);
+        tiles += nt;
+    }
+    const size_t part = 3 * (size_t)tiles * std::max(1, pl->max_E);
+    PT_HIP(hipSetDevice(pl->ctx->device));
+    PT_HIP(hipDeviceSynchronize());  // no launch of this plan may still read the old tiles
+    if ((size_t)tiles > pl->tile_cap) {
+        int32_t *p = nullptr;
+        pt_status st = dev_alloc(pl, &p, sizeof(int32_t) * tiles);
+        if (st) return st;
+        pl->d_tile_tree = p;
+        pl->tile_cap = (size_t)tiles;
+    }
+    if (part > pl->part_cap) {
+        double *p = nullptr;
+        pt_status st = dev_alloc(pl, &p, sizeof(double) * part);
+        if (st) return st;
+        pl->d_part = p;
+        pl->part_cap = part;
+    }
+    PT_HIP(hipMemcpy(pl->d_tile_tree, tile_tree.data(), sizeof(int32_t) * tiles, hipMemcpyHostToDevice));
+    if (pl->kinds & PT_PLAN_LOGLIK)
+        PT_HIP(hipMemcpy(pl->d_trees_ll, tll.data(), sizeof(TreeDev) * B, hipMemcpyHostToDevice));
+    if (pl->kinds & PT_PLAN_GRAD)
+        PT_HIP(hipMemcpy(pl->d_trees_gr, tgr.data(), sizeof(TreeDev) * B, hipMemcpyHostToDevice));
+    pl->tll_h = tll;
+    pl->tgr_h = tgr;
+    pl->n_tiles = tiles;
+    pl->tile_pats = pats;
+    for (auto &kv : pl->execs) (void)hipGraphExecDestroy(kv.second);
+    pl->execs.clear();
     return PT_OK;
 }
 
@@ -606,6 +666,8 @@ pt_status plan_build(pt_ctx *ctx, pt_aln *const *alns, int32_t n_alns, const pt_
         if ((st = dev_alloc(pl.get(), &pl->d_tile_tree, sizeof(int32_t) * tiles))) return st;
         PT_HIP(hipMemcpy(pl->d_tile_tree, tile_tree.data(), sizeof(int32_t) * tiles, hipMemcpyHostToDevice));
         if ((st = dev_alloc(pl.get(), &pl->d_part, sizeof(double) * 3 * (size_t)tiles * std::max(1, pl->max_E)))) return st;
+        pl->tile_cap = (size_t)tiles;
+        pl->part_cap = 3 * (size_t)tiles * std::max(1, pl->max_E);
     }
     if (kinds & PT_PLAN_OPTIMIZE) {
         std::vector<int32_t> order(B);
@@ -653,6 +715,11 @@ pt_status plan_build(pt_ctx *ctx, pt_aln *const *alns, int32_t n_alns, const pt_
             if (st) st = configure_shape(pl.get(), bs);
         if (st) return st;
     }
+    if (kinds & (PT_PLAN_LOGLIK | PT_PLAN_GRAD)) {
+        auto it = ctx->tuned_tiles.find(std::make_tuple(precision, pl->kp, pl->max_P, pl->max_E));
+        if (it != ctx->tuned_tiles.end() && it->second != pl->tile_pats)
+            if ((st = set_tile_pats(pl.get(), it->second))) return st;
+    }
     *out = pl.release();
     return PT_OK;
 }
@@ -689,7 +756,8 @@ pt_status enqueue(pt_plan *pl, int kind, const double *brlen_c, double *brlen, c
         pt::BatchArgs a = batch_args(pl, g ? pl->d_trees_gr : pl->d_trees_ll, g ? std::max(1, pl->max_E) : 1);
         if ((e = pt::launch_pmat(a, brlen_c, s)) != hipSuccess) goto bad;
         if (!reg_ll) {
-            if ((e = pt::launch_tiles(pl->precision, pl->kp, a, brlen_c, pl->lds_tiles, s)) != hipSuccess) goto bad;
+            if ((e = pt::launch_tiles(pl->precision, pl->kp, pl->tile_pats, a, brlen_c, pl->lds_tiles, s)) != hipSuccess)
+                goto bad;
             if ((e = pt::launch_reduce(g, a, lnl, grad, hess, s)) != hipSuccess) goto bad;
         }
         // lnL with every partial in FP64 registers: the likelihood call
@@ -1250,6 +1318,71 @@ pt_status pt_plan_set_launch(pt_plan *plan, int32_t block, int32_t groups) {
     }
     for (auto &kv : plan->execs) (void)hipGraphExecDestroy(kv.second);
     plan->execs.clear();
+    return PT_OK;
+}
+
+pt_status pt_plan_set_tile_patterns(pt_plan *plan, int32_t patterns) {
+    if (!plan) return fail(PT_EINVAL, "plan is NULL");
+    return set_tile_pats(plan, patterns);
+}
+
+pt_status pt_plan_tile_patterns(const pt_plan *plan, int32_t *patterns) {
+    if (!plan || !patterns) return fail(PT_EINVAL, "NULL argument");
+    *patterns = plan->tile_pats;
+    return PT_OK;
+}
+
+pt_status pt_plan_autotune_tiles(pt_plan *plan, const double *d_brlen, int32_t *patterns_out) {
+    if (!plan || !(plan->kinds & (PT_PLAN_LOGLIK | PT_PLAN_GRAD)))
+        return fail(PT_EINVAL, "plan was not created with PT_PLAN_LOGLIK or PT_PLAN_GRAD");
+    if (plan->n_trees == 0) {
+        if (patterns_out) *patterns_out = plan->tile_pats;
+        return PT_OK;
+    }
+    if (!d_brlen) return fail(PT_EINVAL, "d_brlen is NULL");
+    PT_HIP(hipSetDevice(plan->ctx->device));
+    hipStream_t s = plan->ctx->stream;
+    // time what the tiles run: the gradient when the plan has one, else the
+    // stored likelihood pass
+    const int kind = (plan->kinds & PT_PLAN_GRAD) ? PT_PLAN_GRAD : PT_PLAN_LOGLIK;
+    const int ll_prev = plan->ll_stored;
+    if (kind == PT_PLAN_LOGLIK) plan->ll_stored = 1;
+    double *d_l = nullptr, *d_g = nullptr;
+    pt_status st = dev_alloc(plan, &d_l, sizeof(double) * plan->n_trees);
+    if (!st && kind == PT_PLAN_GRAD) st = dev_alloc(plan, &d_g, sizeof(double) * std::max<int64_t>(1, plan->n_edges));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int best = plan->tile_pats;
+    float best_ms = 1e30f;
+    if (!st && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
+        st = fail(PT_EDEVICE, "hipEventCreate failed");
+    for (int pats : {256, 128, 64}) {
+        if (st) break;
+        if ((st = set_tile_pats(plan, pats))) break;
+        float trial = 1e30f;
+        for (int rep = 0; rep < 3 && !st; ++rep) {
+            if (hipEventRecord(e0, s) != hipSuccess) { st = fail(PT_EDEVICE, "hipEventRecord failed"); break; }
+            st = enqueue(plan, kind, d_brlen, nullptr, nullptr, d_l, nullptr, nullptr, d_g, nullptr, s);
+            if (st) break;
+            float ms = 0;
+            if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                st = fail(PT_EDEVICE, "event timing failed");
+                break;
+            }
+            if (rep > 0) trial = std::min(trial, ms);  // the first run warms up
+        }
+        if (!st && trial < best_ms) {
+            best_ms = trial;
+            best = pats;
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    plan->ll_stored = ll_prev;
+    if (st) return st;
+    if ((st = set_tile_pats(plan, best))) return st;
+    plan->ctx->tuned_tiles[std::make_tuple(plan->precision, plan->kp, plan->max_P, plan->max_E)] = best;
+    if (patterns_out) *patterns_out = best;
     return PT_OK;
 }
 

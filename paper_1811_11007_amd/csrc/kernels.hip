@@ -1853,10 +1853,18 @@ hipError_t launch_pmat(const BatchArgs &a, const double *brlen, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_tiles(int precision, int kp, const BatchArgs &a, const double *brlen, size_t lds, hipStream_t s) {
+bool tile_patterns_supported(int pats) { return pats == 64 || pats == 128 || pats == 256; }
+
+hipError_t launch_tiles(int precision, int kp, int tile_pats, const BatchArgs &a, const double *brlen, size_t lds,
+                        hipStream_t s) {
     if (a.n_tiles <= 0) return hipSuccess;
-    PT_KP_SWITCH(return precision == PT_FP32 ? launch_tiles_t<float, kTileBlock, KP>(a, brlen, lds, s)
-                                             : launch_tiles_t<double, kTileBlock, KP>(a, brlen, lds, s));
+#define PT_TILES_BS(BSZ)                                                                             \
+    PT_KP_SWITCH(return precision == PT_FP32 ? launch_tiles_t<float, BSZ, KP>(a, brlen, lds, s) \
+                                             : launch_tiles_t<double, BSZ, KP>(a, brlen, lds, s))
+    if (tile_pats == 64) PT_TILES_BS(64);
+    if (tile_pats == 128) PT_TILES_BS(128);
+    if (tile_pats == 256) PT_TILES_BS(256);
+#undef PT_TILES_BS
     return hipErrorInvalidValue;
 }
 

@@ -61,8 +61,11 @@ size_t optimize_spill_bytes(int precision, int block, int kp, bool tab_lds, bool
 hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
 hipError_t launch_pmat(const BatchArgs &a, const double *brlen, hipStream_t s);
 // lds_bytes: the largest tree's transition matrices (used with FP64 partials).
-hipError_t launch_tiles(int precision, int kp, const BatchArgs &a, const double *brlen, size_t lds_bytes,
-                        hipStream_t s);
+// tile_pats: patterns per tile (= threads per block, one pattern each): 64,
+// 128 or 256 (kTileBlock, the default).
+bool tile_patterns_supported(int pats);
+hipError_t launch_tiles(int precision, int kp, int tile_pats, const BatchArgs &a, const double *brlen,
+                        size_t lds_bytes, hipStream_t s);
 // Register-resident lnL (k_loglik_reg): patterns per tile for a padded
 // category count, its LDS for n taxa and a stack of `depth` slots, and the
 // launch (one block per tile; a.tile_tree, a.part, a.n_tiles and
