@@ -67,6 +67,12 @@ const char *pt_last_error(void);
 typedef struct pt_ctx pt_ctx;
 pt_status pt_ctx_create(int32_t device, pt_ctx **out);
 void pt_ctx_destroy(pt_ctx *ctx);
+/* Shader clocks after which a cross-block wait of the optimisation kernel
+ * (trees split over several blocks, pt_plan_set_launch) gives up and marks
+ * its tree status 2, for launches made from now on with this context;
+ * cycles <= 0 restores the default, 2^27 (about 50 ms).  A small limit lets
+ * a caller test its handling of status 2; every wait stays bounded. */
+pt_status pt_ctx_set_group_wait(pt_ctx *ctx, int64_t cycles);
 
 /* ------------------------------------------------------------------- model */
 
@@ -153,9 +159,11 @@ pt_status pt_batch_loglik(pt_ctx *ctx, pt_aln *const *alns, int32_t n_alns,
  * (NULL = all) selects the edges that move (partial optimisation, the
  * paper's radius option).  opt NULL = pt_opt_default(precision).
  * passes_out / status_out may be NULL; status 0 = the stopping rule was met,
- * 1 = max_passes reached first (not an error).  PT_EINTERNAL, outputs
- * untouched, if a tree split over several blocks (pt_plan_set_launch) had a
- * cross-block wait time out (status 2 in the plan calls). */
+ * 1 = max_passes reached first (not an error).  When the trees of a chunk
+ * are split over several blocks (pt_plan_set_launch) and a cross-block wait
+ * times out (other work holding compute units; status 2 in the plan calls),
+ * the chunk is optimised again from its starting lengths with one block per
+ * tree, and those results are returned. */
 pt_status pt_batch_optimize_branches(pt_ctx *ctx, pt_aln *const *alns, int32_t n_alns,
                                      const pt_trees *trees, double *brlen_inout,
                                      const uint8_t *opt_mask, const pt_opt *opt,

@@ -21,7 +21,7 @@ PT_PLAN_LOGLIK, PT_PLAN_OPTIMIZE, PT_PLAN_GRAD = 1, 2, 4
 PT_LOGLIK_REGISTERS, PT_LOGLIK_STORED = 0, 1
 
 EXPORTS = [
-    "pt_last_error", "pt_ctx_create", "pt_ctx_destroy", "pt_aln_create", "pt_aln_destroy",
+    "pt_last_error", "pt_ctx_create", "pt_ctx_destroy", "pt_ctx_set_group_wait", "pt_aln_create", "pt_aln_destroy",
     "pt_opt_default", "pt_batch_loglik", "pt_batch_optimize_branches", "pt_batch_branch_grad",
     "pt_batch_loglik_noalloc",
     "pt_plan_create", "pt_plan_destroy", "pt_plan_set_graphs", "pt_plan_loglik",
@@ -107,6 +107,7 @@ def lib():
         L.pt_plan_loglik.argtypes = [vp, vp, vp, vp]
         L.pt_plan_optimize.argtypes = [vp, vp, P(pt_opt), vp, vp, vp, vp]
         L.pt_plan_set_alpha.argtypes = [vp, vp, vp]
+        L.pt_ctx_set_group_wait.argtypes = [vp, ctypes.c_int64]
         L.pt_plan_set_tile_patterns.argtypes = [vp, i32]
         L.pt_plan_tile_patterns.argtypes = [vp, P(i32)]
         L.pt_plan_autotune_tiles.argtypes = [vp, vp, P(i32)]
@@ -169,6 +170,11 @@ class Context:
     def __init__(self, device: int = 0):
         self.h = ctypes.c_void_p()
         check(lib().pt_ctx_create(device, ctypes.byref(self.h)))
+
+    def set_group_wait(self, cycles):
+        """Shader clocks before a cross-block wait of the optimiser gives up
+        (<= 0: the default); see pt_ctx_set_group_wait."""
+        check(lib().pt_ctx_set_group_wait(self.h, int(cycles)))
 
     def close(self):
         if self.h:

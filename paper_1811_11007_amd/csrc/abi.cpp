@@ -85,6 +85,9 @@ struct pt_ctx {
     // size for every batch, and a fresh hipMalloc / hipFree of tens of GB
     // each time cost far more than the optimisation itself
     std::shared_ptr<DevicePool> pool = std::make_shared<DevicePool>();
+    // shader clocks before a cross-block wait of the optimisation kernel
+    // gives up (pt_ctx_set_group_wait; 0: the kernel's default)
+    long long group_wait = 0;
     // this device's no-allocation workspace (pt_batch_loglik_noalloc)
     void *noalloc = nullptr;
     std::string noalloc_err;
@@ -782,6 +785,7 @@ pt_status enqueue(pt_plan *pl, int kind, const double *brlen_c, double *brlen, c
         a.prof = pl->d_prof;
         a.groups = pl->opt_groups;
         a.gsync = pl->d_gsync;
+        a.wait_cycles = pl->ctx->group_wait;
         if ((e = pt::launch_fill_i32(pl->d_queue, 0, 1, s)) != hipSuccess) goto bad;
         if (pl->opt_groups > 1 &&
             (e = pt::launch_fill_i32(reinterpret_cast<int32_t *>(pl->d_gsync), 0,
@@ -924,6 +928,25 @@ pt_status host_batch(pt_ctx *ctx, pt_aln *const *alns, int32_t n_alns, const pt_
             if ((st = dev_alloc(pl.get(), &d_ps, sizeof(int32_t) * std::max(1, nb)))) return st;
             if ((st = dev_alloc(pl.get(), &d_st, sizeof(int32_t) * std::max(1, nb)))) return st;
             st = enqueue(pl.get(), kind, nullptr, d_len, &op, d_lnl, d_ps, d_st, nullptr, nullptr, ctx->stream);
+            if (!st && pl->opt_groups > 1) {
+                // A tree split over several blocks needs all of them resident
+                // at once; when other work holds compute units a cross-block
+                // wait times out (status 2).  The chunk is then optimised
+                // again from its starting lengths with one block per tree.
+                std::vector<int32_t> h_st(nb);
+                PT_HIP(hipMemcpyAsync(h_st.data(), d_st, sizeof(int32_t) * nb, hipMemcpyDeviceToHost, ctx->stream));
+                PT_HIP(hipStreamSynchronize(ctx->stream));
+                if (std::find(h_st.begin(), h_st.end(), 2) != h_st.end()) {
+                    st = configure_shape(pl.get(), 512, 1);
+                    if (st) st = configure_shape(pl.get(), 256, 1);
+                    if (st) return st;
+                    if (ne)
+                        PT_HIP(hipMemcpyAsync(d_len, cl.data(), sizeof(double) * ne, hipMemcpyHostToDevice,
+                                              ctx->stream));
+                    st = enqueue(pl.get(), kind, nullptr, d_len, &op, d_lnl, d_ps, d_st, nullptr, nullptr,
+                                 ctx->stream);
+                }
+            }
         } else if (kind == PT_PLAN_GRAD) {
             if ((st = dev_alloc(pl.get(), &d_g, sizeof(double) * std::max<int64_t>(1, ne)))) return st;
             if (hess_out && (st = dev_alloc(pl.get(), &d_h, sizeof(double) * std::max<int64_t>(1, ne)))) return st;
@@ -1318,6 +1341,12 @@ pt_status pt_plan_set_launch(pt_plan *plan, int32_t block, int32_t groups) {
     }
     for (auto &kv : plan->execs) (void)hipGraphExecDestroy(kv.second);
     plan->execs.clear();
+    return PT_OK;
+}
+
+pt_status pt_ctx_set_group_wait(pt_ctx *ctx, int64_t cycles) {
+    if (!ctx) return fail(PT_EINVAL, "ctx is NULL");
+    ctx->group_wait = cycles > 0 ? (long long)cycles : 0;
     return PT_OK;
 }
 

@@ -266,6 +266,7 @@ struct GroupS {  // in LDS; written by lane 0 of the block's first wave
     int G, g;
     int seq, is_broken;
     unsigned long long *broken, *slots;
+    long long wait;  // shader clocks before a wait gives up
     double tot[3];
 };
 
@@ -293,7 +294,7 @@ __device__ inline void group_exchange(GroupS *gs, double a, double b, double c) 
                 ok = (va & 3ull) == want && (vb & 3ull) == want && (vc & 3ull) == want;
             }
             if (__all(ok)) break;
-            if (clock64() - t0 > kGroupWaitCycles) {
+            if (clock64() - t0 > gs->wait) {
                 if (lane == 0) {
                     store_agent(gs->broken, 1ull);
                     gs->is_broken = 1;
@@ -1562,6 +1563,7 @@ __global__ void __launch_bounds__(BS) k_optimize(const BatchArgs a, double *brle
             gsh.is_broken = 0;
             gsh.broken = base;
             gsh.slots = base + 1;
+            gsh.wait = a.wait_cycles > 0 ? a.wait_cycles : kGroupWaitCycles;
         }
         __syncthreads();
         for (int x = tid; x < E * KP * 16; x += BS) {

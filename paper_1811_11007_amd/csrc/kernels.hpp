@@ -30,6 +30,8 @@ struct BatchArgs {
     unsigned long long *gsync;  // optimisation with groups > 1: per-tree cross-block words, zeroed
     int32_t reg_depth;          // register-resident lnL: stack slots of the deepest tree
     const double *ident;        // register-resident lnL: the 4x4 identity (16 doubles)
+    long long wait_cycles;      // optimisation with groups > 1: shader clocks before a
+                                // cross-block wait gives up (0: kGroupWaitCycles)
 };
 
 // Optimisation with several blocks per tree: at most kGroupBlocksMax blocks,

@@ -180,3 +180,33 @@ def test_relaxed_steps_reach_the_oracle_optimum(ctx):
     assert np.all(s == 0), s
     assert np.max(np.abs(l - ref)) < 1e-7
     plan.close()
+
+
+def test_timed_out_waits_fall_back_to_one_block_per_tree(ctx):
+    """With the cross-block wait limit forced down to a few clocks from the
+    host (every wait stays bounded, so every kernel still ends), a plan call
+    on trees split over several blocks reports status 2 and NaN for the trees
+    whose waits ran out, and the synchronous call re-runs its chunk with one
+    block per tree and returns the oracle's optima with status 0."""
+    aln, ne, nbl, ref = c2_batch()
+    A = pt.Alignment.from_synth(ctx, aln)
+    T = pt.Trees(list(ne))
+    ctx.set_group_wait(8)
+    try:
+        plan = pt.Plan(ctx, [A], T, pt.PT_PLAN_OPTIMIZE, pt.PT_FP64)
+        plan.set_launch(256, 4)
+        lnl, st, _ = run_plan(plan, nbl, len(ne), replays=1)[0]
+        broken = st == 2
+        say("forced time-outs: %d of %d trees status 2" % (broken.sum(), len(ne)))
+        assert np.all((st == 0) | broken)
+        assert np.all(np.isnan(lnl[broken]))
+        plan.close()
+        for prec, ok in ((pt.PT_FP64, lambda l: np.max(np.abs(l - ref) / np.abs(ref)) < FP64_REL),
+                         (pt.PT_FP32, lambda l: np.max(np.abs(l - ref)) < FP32_ABS)):
+            l, b, ps, s = pt.pt_batch_optimize_branches(ctx, [A], T, np.ravel(nbl), precision=prec)
+            assert np.all(s == 0), s
+            assert ok(l)
+    finally:
+        ctx.set_group_wait(0)
+    l, b, ps, s = pt.pt_batch_optimize_branches(ctx, [A], T, np.ravel(nbl), precision=pt.PT_FP64)
+    assert np.all(s == 0) and np.max(np.abs(l - ref) / np.abs(ref)) < FP64_REL
