@@ -218,8 +218,10 @@ def main():
     traffic = None
     if os.path.exists(TRAFFIC):
         tr = json.load(open(TRAFFIC))
-        if tr.get("kernel_hash") == kernel_hash() and "optimize_c2_fp32" in tr:
-            traffic = tr["optimize_c2_fp32"]["bytes_per_launch"]
+        if tr.get("kernel_hash") == kernel_hash():
+            # the counters of the launch shape this run's autotuner chose
+            shape = "%dx%d" % (r32["shape"][0], r32["shape"][2])
+            traffic = tr.get("optimize_c2_fp32", {}).get(shape, {}).get("bytes_per_launch")
     out = {
         "metric": "optimized topologies/s at |dlnL|<1e-4; pruning HBM GB/s vs peak",
         "value": round(value if ok else 0.0, 3),
@@ -493,11 +495,12 @@ def main():
                 # the whole call's time (a lower bound for the kernel alone)
                 def counter(key, ms):
                     return round(tr[key]["bytes_per_launch"] / (ms / 1e3) / 1e9, 1) if key in tr else None
-                out["pruning"]["counter_GBs"] = counter("tiles_512_fp32", ms3)
-                out["pruning"]["fp64"]["counter_GBs"] = counter("tiles_512_fp64", ms3d)
+                # (the tile kernels' counters at the tile size this run chose)
+                out["pruning"]["counter_GBs"] = counter("tiles_512_fp32_t%d" % tiles3[pt.PT_FP32], ms3)
+                out["pruning"]["fp64"]["counter_GBs"] = counter("tiles_512_fp64_t%d" % tiles3[pt.PT_FP64], ms3d)
                 out["loglik_registers"]["roofline"]["traffic"] = tr.get("loglik_reg_512", {}).get("bytes_per_launch")
                 out["batched_512"]["counter_GBs"] = counter("optimize_512_fp32", ms3o)
-                out["gradient"]["counter_GBs"] = counter("grad_256_fp32", ms4)
+                out["gradient"]["counter_GBs"] = counter("grad_256_fp32_t%d" % tiles4, ms4)
 
     if not args.no_cpu:
         log("oracle cpu baseline ...")
