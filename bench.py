@@ -416,6 +416,7 @@ def main():
                           "frac_of_peak": round(by3 / (ms3 / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
                           "counter_GBs": None,
                           "max_abs_dlnl_vs_oracle": float(np.max(np.abs(l3 - start3))),
+                          "all_within_1e-4": bool(np.max(np.abs(l3 - start3)) <= 1e-4),
                           "note": "graph of k_pmat + k_tiles + k_reduce",
                           "patterns_per_tile": tiles3.get(pt.PT_FP32),
                           "fp64": {"ms_per_call": round(ms3d, 4), "algorithmic_bytes": by3d,
