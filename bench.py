@@ -229,7 +229,7 @@ def main():
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(r32["ms"], 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32 partials / f64 arithmetic",
+        "dtype": "f32 partials and partial updates / f64 Newton sums and lnL",
         "data": "synthetic (seeded GTR+G4 simulation; no dataset)",
         "config": {"workload": "48 NNI neighbours of a hill-climbed 27-taxon tree, 1949 sites "
                                "(%d patterns) GTR+G4, full branch optimisation" % aln.n_patterns,

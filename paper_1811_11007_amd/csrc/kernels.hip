@@ -380,6 +380,16 @@ struct Side {
         if constexpr (TIP) tip_vec(code, x);
         else Store<T>::widen(r[k], x);
     }
+    // the same state vector in FP32 (FP32 partials only)
+    __device__ inline void getf(int k, float x[4]) const {
+        if constexpr (TIP) {
+            x[0] = (float)(code & 1u); x[1] = (float)((code >> 1) & 1u);
+            x[2] = (float)((code >> 2) & 1u); x[3] = (float)((code >> 3) & 1u);
+        } else {
+            static_assert(std::is_same<T, float>::value, "FP32 state vectors of FP32 partials only");
+            x[0] = r[k].x; x[1] = r[k].y; x[2] = r[k].z; x[3] = r[k].w;
+        }
+    }
 };
 
 // Where an update reads its transition matrices (PM):
@@ -389,7 +399,8 @@ struct Side {
 //             scalar loads into scalar registers instead of being broadcast
 //             to every lane;
 //   kPmLds32  FP32 copy in LDS (half the broadcast bytes), for FP32 partials
-//             in the optimisation loop.
+//             in the optimisation loop, whose updates then compute in FP32
+//             (update_pattern_f32).
 //   kPmGlobal FP64 matrices in global memory (the FP64 evaluation that ends
 //             an optimisation with FP32 partials).
 enum : int { kPmLds = 0, kPmConst = 1, kPmLds32 = 2, kPmGlobal = 3 };
@@ -413,6 +424,44 @@ template <int PM, typename V>
 __device__ inline typename PmPtr<PM>::type pm_base(const V &v) {
     if constexpr (PM == kPmLds32) return v.pmf;
     else return (typename PmPtr<PM>::type)v.pm;
+}
+
+// One pattern of an OP_UPDATE in FP32 arithmetic, for FP32 partials in the
+// optimisation loop (matrices from the FP32 LDS copy): the same products and
+// scaling rule as update_pattern, computed in the precision the partial is
+// stored in, so no entry is widened to FP64 and narrowed back.  The new
+// partial of every category goes to out[k] as stored; returns the scaler
+// count.  (The lnL an optimisation reports comes from FP64 partials at the
+// final lengths, and the Newton sums stay FP64.)
+template <int KP, class SA, class SB>
+__device__ inline int update_pattern_f32(const TreeView<float> &v, const Op &op, const SA &sa, const SB &sb,
+                                         float4 out[KP]) {
+    const float *pm = v.pmf;
+    const float thr = 0x1p-64f, up = 0x1p64f;  // Store<float>::kScaleExp
+    float o[KP][4];
+    float mx = 0.0f;
+#pragma unroll
+    for (int k = 0; k < KP; ++k) {
+        float xa[4], xb[4];
+        sa.getf(k, xa);
+        sb.getf(k, xb);
+        const float *Pa = pm + ((size_t)op.ea * KP + k) * 16;
+        const float *Pb = pm + ((size_t)op.eb * KP + k) * 16;
+        const bool live = k < v.K;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const float xsa = Pa[i * 4] * xa[0] + Pa[i * 4 + 1] * xa[1] + Pa[i * 4 + 2] * xa[2] + Pa[i * 4 + 3] * xa[3];
+            const float xsb = Pb[i * 4] * xb[0] + Pb[i * 4 + 1] * xb[1] + Pb[i * 4 + 2] * xb[2] + Pb[i * 4 + 3] * xb[3];
+            o[k][i] = live ? xsa * xsb : 0.0f;
+            mx = fmaxf(mx, o[k][i]);
+        }
+    }
+    int c = sa.c + sb.c;
+    const float f = mx < thr && mx > 0.0f ? up : 1.0f;
+    c += f != 1.0f;
+#pragma unroll
+    for (int k = 0; k < KP; ++k) out[k] = make_float4(o[k][0] * f, o[k][1] * f, o[k][2] * f, o[k][3] * f);
+    return c;
 }
 
 // One pattern of an OP_UPDATE from its two fetched sides, for the fused
@@ -473,6 +522,15 @@ __device__ inline void update_sides(const TreeView<T> &v, const Op &op, int base
         Side<T, KP, TB> sb;
         sa.fetch(v, op.a, p);
         sb.fetch(v, op.b, p);
+        if constexpr (PM == kPmLds32) {
+            float4 out[KP];
+            const int c = update_pattern_f32<KP>(v, op, sa, sb, out);
+#pragma unroll
+            for (int k = 0; k < KP; ++k)
+                if (k < v.K) Store<T>::store_raw(slot_ptr<T, KP>(v, op.dst, k, p), out[k]);
+            v.cnt[(size_t)op.dst * v.P + p] = (uint16_t)c;
+            continue;
+        }
         double o[KP][4];
         double mx = 0.0;
 #pragma unroll
@@ -770,7 +828,9 @@ __device__ inline double update_table_sides(const TreeView<T> &v, const Op &op, 
         so.fetch(v, other, p);
         const double w = ldg(v.w + p);
         Side<T, KP, false> made;
-        {
+        if constexpr (PM == kPmLds32) {
+            made.c = update_pattern_f32<KP>(v, op, sa, sb, made.r);
+        } else {
             double o[KP][4];
             made.c = update_pattern<T, KP, PM>(v, op, sa, sb, o);
 #pragma unroll
