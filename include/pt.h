@@ -126,7 +126,11 @@ typedef struct {
  * second derivative) is at least tol_lnl / (2n - 3), or the model is not
  * concave there (with FP32 partials a length whose optimum is t_min would
  * otherwise keep moving on and off the bound by noise-level amounts that
- * change nothing).
+ * change nothing).  With FP32 partials that exemption applies to every
+ * change, and a pass's rise is the sum over its steps of the quadratic
+ * model's value d1 dt + d2 dt^2 / 2 at each step's start (FP32 partials
+ * resolve lnL only to about 1e-4, above tol_lnl, while the model sums are
+ * free of that rounding noise).
  * The objective is lnL (prior_rate = 0, maximum likelihood) or, with
  * prior_rate > 0, lnL plus the log density of independent Exponential
  * (prior_rate) priors on every length, sum_e (log prior_rate - prior_rate
@@ -142,9 +146,8 @@ typedef struct {
 
 /* Defaults for a precision: t_min 1e-8, t_max 100, max_passes 200,
  * max_newton 32, prior_rate 0; FP64 tol_lnl 1e-8, tol_t 1e-5, tol_newton 1e-9; FP32
- * tol_lnl 1e-5, tol_t 1e-3, tol_newton 1e-6 (FP32 partials cannot resolve
- * lnL changes much below 1e-5 on alignments of ~1e3 patterns; the reported
- * lnL is evaluated from FP64 partials at the final lengths). */
+ * tol_lnl 1e-5, tol_t 1e-3, tol_newton 1e-6 (the reported lnL is
+ * evaluated from FP64 partials at the final lengths). */
 void pt_opt_default(int32_t precision, pt_opt *out);
 
 /* --------------------------------------------------- host-pointer batches */

@@ -96,11 +96,13 @@ struct ModelS {
     double Uinv[16];
     double lam[4];
     double rate[kMaxCats];
+    float Wf[16];    // W rounded to FP32 (the FP32 tables of the optimisation loop)
 };
 
 __device__ inline void model_to_lds(const AlnDev *aln, ModelS *m) {
     for (int x = threadIdx.x; x < 16; x += blockDim.x) {
         m->W[x] = aln->W[x];
+        m->Wf[x] = (float)aln->W[x];
         m->U[x] = aln->U[x];
         m->Uinv[x] = aln->Uinv[x];
     }
@@ -605,6 +607,44 @@ __device__ inline void coeffs_x(const ModelS *md, const double xa[4], const doub
     }
 }
 
+// The same coefficients in FP32, for tables stored in FP32 (the optimisation
+// loop with FP32 partials): computed in the precision they are stored in.
+__device__ inline void coeffs_xf(const ModelS *md, const float xa[4], const float xb[4], float s[4]) {
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        float ua = 0.0f, vb = 0.0f;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const float wim = md->Wf[i * 4 + m];
+            ua += wim * xa[i];
+            vb += wim * xb[i];
+        }
+        s[m] = ua * vb;
+    }
+}
+
+// One category's table coefficients for one pattern, stored at dst and
+// returned (as stored) in sk: in FP32 from the FP32 values of the sides when
+// the table is FP32, else in FP64.
+template <typename T, class SA, class SB>
+__device__ inline void table_coeffs(const ModelS *md, const SA &sa, const SB &sb, int k, T *dst, double sk[4]) {
+    if constexpr (std::is_same<T, float>::value) {
+        float xa[4], xb[4], s[4];
+        sa.getf(k, xa);
+        sb.getf(k, xb);
+        coeffs_xf(md, xa, xb, s);
+        *reinterpret_cast<float4 *>(dst) = make_float4(s[0], s[1], s[2], s[3]);
+#pragma unroll
+        for (int m = 0; m < 4; ++m) sk[m] = s[m];
+    } else {
+        double xa[4], xb[4];
+        sa.get(k, xa);
+        sb.get(k, xb);
+        coeffs_x(md, xa, xb, sk);
+        Store<T>::store(dst, sk);
+    }
+}
+
 // This thread's contributions to lnL, d1 and d2 across an edge whose sides
 // are of kinds TA / TB, with the exponentials of its length in wx.
 template <typename T, int BS, int KP, bool TA, bool TB>
@@ -668,6 +708,7 @@ __device__ inline Sums3 eval_edge(const TreeView<T> &v, int a, int b, int base, 
 struct EdgeResult {
     double t, lnl;
     double gain;  // the objective's gain from the step by its quadratic model at the start, or +inf
+    double rise;  // the same model's value for the step, whatever the sign of its second derivative
     int parity, iters;
     long long cyc_table, cyc_iters;
 };
@@ -691,11 +732,8 @@ __device__ inline void table_row(const TreeView<T> &v, const SA &sa, const SB &s
 #pragma unroll
     for (int k = 0; k < KP; ++k) {
         if (k < v.K) {
-            double xa[4], xb[4], sk[4];
-            sa.get(k, xa);
-            sb.get(k, xb);
-            coeffs_x(md, xa, xb, sk);
-            Store<T>::store(tab + ((size_t)k * rows + p) * 4, sk);
+            double sk[4];
+            table_coeffs<T>(md, sa, sb, k, tab + ((size_t)k * rows + p) * 4, sk);
             if constexpr (FUSE) {
 #pragma unroll
                 for (int m = 0; m < 4; ++m) {
@@ -751,11 +789,8 @@ __device__ inline double table_sides(const TreeView<T> &v, int a, int b, int ni,
 #pragma unroll
         for (int k = 0; k < KP; ++k) {
             if (k < v.K) {
-                double xa[4], xb[4], sk[4];
-                sa0.get(k, xa);
-                sb0.get(k, xb);
-                coeffs_x(md, xa, xb, sk);
-                Store<T>::store(tab + ((size_t)k * rows + p0) * 4, sk);
+                double sk[4];
+                table_coeffs<T>(md, sa0, sb0, k, tab + ((size_t)k * rows + p0) * 4, sk);
                 if constexpr (FUSE) {
 #pragma unroll
                     for (int m = 0; m < 4; ++m) {
@@ -780,11 +815,8 @@ __device__ inline double table_sides(const TreeView<T> &v, int a, int b, int ni,
 #pragma unroll
             for (int k = 0; k < KP; ++k) {
                 if (k < v.K) {
-                    double xa[4], xb[4], sk[4];
-                    sa1.get(k, xa);
-                    sb1.get(k, xb);
-                    coeffs_x(md, xa, xb, sk);
-                    Store<T>::store(tab + ((size_t)k * rows + p1) * 4, sk);
+                    double sk[4];
+                    table_coeffs<T>(md, sa1, sb1, k, tab + ((size_t)k * rows + p1) * 4, sk);
                     if constexpr (FUSE) {
 #pragma unroll
                         for (int m = 0; m < 4; ++m) {
@@ -1108,7 +1140,8 @@ __device__ inline EdgeResult newton_edge(const TreeView<T> &v, int a, int b, dou
     r.cyc_iters = clock64() - c1;
     {
         const double dt = t - t_in;
-        r.gain = d2_0 < 0.0 ? d1_0 * dt + 0.5 * d2_0 * dt * dt : INFINITY;
+        r.rise = d1_0 * dt + 0.5 * d2_0 * dt * dt;
+        r.gain = d2_0 < 0.0 ? r.rise : INFINITY;
     }
     return r;
 }
@@ -1654,6 +1687,7 @@ __global__ void __launch_bounds__(BS) k_optimize(const BatchArgs a, double *brle
             const int o0 = first ? td.op_first : td.op_steady;
             const int no = first ? td.n_first : td.n_steady;
             double max_rel = 0.0;
+            double pass_gain = 0.0;  // the steps' predicted gains (FP32 partials)
             EdgePre pre;
             bool have_pre = false;
             for (int o = 0; o < no; ++o) {
@@ -1711,9 +1745,24 @@ __global__ void __launch_bounds__(BS) k_optimize(const BatchArgs a, double *brle
                 // moving the length on and off the bound by amounts tiny in
                 // absolute terms but large relative to the 1e-6 floor of the
                 // relative change, for no gain.
+                //
+                // With FP32 partials the same holds away from the bounds: a
+                // pass's lnL is resolved only to about 1e-4 (rounding of the
+                // stored partials; measured on the 27-taxon trees), above
+                // tol_lnl, and a short length keeps moving by about tol_t
+                // relative on derivative noise for gains near 1e-9.  There a
+                // step counts against convergence only when its gain is not
+                // negligible, and the pass's lnL increase is taken as the sum
+                // over its steps of the quadratic model's value (which sees
+                // no rounding noise) instead of the difference of two noisy
+                // lnL values.  A step not concave at its start still counts
+                // its model value there (a flat long length settles with a
+                // second derivative at the noise level, of either sign), and
+                // always counts against convergence by its length change.
                 const bool at_bound = t0 <= opt.t_min || t0 >= opt.t_max || r.t <= opt.t_min || r.t >= opt.t_max;
-                if (!(at_bound && r.gain < opt.tol_lnl / E))
+                if (!((kF32 || at_bound) && r.gain < opt.tol_lnl / E))
                     max_rel = fmax(max_rel, fabs(r.t - t0) / fmax(t0, 1e-6));
+                pass_gain += r.rise;
                 if (r.t != t0) {
                     if (tid == 0) tl[e] = r.t;
                     if constexpr (KP * 16 <= 64) {
@@ -1739,7 +1788,8 @@ __global__ void __launch_bounds__(BS) k_optimize(const BatchArgs a, double *brle
             }
             ++passes;
             cur += log_prior(tl, E, opt.prior_rate);
-            if (td.n_steady == 0 || (cur - prev < opt.tol_lnl && max_rel < opt.tol_t)) {
+            const double rise = kF32 ? pass_gain : cur - prev;
+            if (td.n_steady == 0 || (rise < opt.tol_lnl && max_rel < opt.tol_t)) {
                 converged = true;
                 break;
             }
