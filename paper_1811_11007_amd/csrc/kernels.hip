@@ -117,6 +117,26 @@ __device__ inline X ldg(const X *p) {
     return *(const __attribute__((address_space(1))) X *)p;
 }
 
+// One op of a program.  Programs are never written during a launch, so they
+// are read through the constant address space: scalar loads into SGPRs.
+// (A kernel that stores partials would otherwise read its ops by vector
+// loads, the global memory not being known constant, and wait on the vector
+// memory counter before every branch on the opcode.)
+__device__ inline Op load_op(const Op *ops, int64_t i) {
+    static_assert(sizeof(Op) == 8 * sizeof(int32_t), "an op is eight words");
+    const __attribute__((address_space(4))) int32_t *q = (const __attribute__((address_space(4))) int32_t *)(ops + i);
+    Op op;
+    op.code = q[0];
+    op.dst = q[1];
+    op.a = q[2];
+    op.ea = q[3];
+    op.b = q[4];
+    op.eb = q[5];
+    op.pad0 = q[6];
+    op.pad1 = q[7];
+    return op;
+}
+
 // View of one tree's data for the device functions below.
 template <typename T>
 struct TreeView {
@@ -1280,7 +1300,7 @@ __device__ inline void tiles_body(const BatchArgs &a, const double *brlen) {
     Side<T, KP, false> last;
     int last_dst = -1;
     for (int o = 0; o < td.n_first; ++o) {
-        const Op op = a.ops[td.op_first + o];
+        const Op op = load_op(a.ops, td.op_first + o);
         if (op.code == OP_UPDATE && !kForward) {
             do_update<T, BS, KP, PMK>(v, op, base, kTileItems);
             continue;
@@ -1467,10 +1487,10 @@ __global__ void __launch_bounds__(RegShape<KP>::kThreads) k_loglik_reg(const Bat
     };
     // each op is loaded one step ahead, so its scalar load's round trip
     // overlaps the previous step
-    Op nx = a.ops[td.op_first];
+    Op nx = load_op(a.ops, td.op_first);
     for (int o = 0; o < td.n_first; ++o) {
         const Op op = nx;
-        if (o + 1 < td.n_first) nx = a.ops[td.op_first + o + 1];
+        if (o + 1 < td.n_first) nx = load_op(a.ops, td.op_first + o + 1);
         if (op.code == OP_RPUSH) {
 #pragma unroll
             for (int j = 0; j < NI; ++j)
@@ -1691,7 +1711,7 @@ __global__ void __launch_bounds__(BS) k_optimize(const BatchArgs a, double *brle
             EdgePre pre;
             bool have_pre = false;
             for (int o = 0; o < no; ++o) {
-                const Op op = a.ops[o0 + o];
+                const Op op = load_op(a.ops, o0 + o);
                 if (op.code == OP_UPDATE) {
                     const long long u0 = a.prof ? clock64() : 0;
                     bool fused = false;
@@ -1701,7 +1721,7 @@ __global__ void __launch_bounds__(BS) k_optimize(const BatchArgs a, double *brle
                         // an update making one side of the next edge step:
                         // build that edge's table from it directly
                         if (ni == 1 && o + 1 < no) {
-                            const Op nx = a.ops[o0 + o + 1];
+                            const Op nx = load_op(a.ops, o0 + o + 1);
                             if (nx.code == OP_NEWTON && (nx.a == op.dst || nx.b == op.dst)) {
                                 pre = update_and_table<T, BS, KP, kF32 ? kPmLds32 : kPmLds>(
                                     v, op, nx.a == op.dst ? nx.b : nx.a, tl[nx.dst], tab, wrow, wx, wxf);
@@ -1825,7 +1845,7 @@ __global__ void __launch_bounds__(BS) k_optimize(const BatchArgs a, double *brle
             vd.np = v.np;
             vd.K = v.K;
             for (int o = 0; o < td.n_final; ++o) {
-                const Op op = a.ops[td.op_final + o];
+                const Op op = load_op(a.ops, td.op_final + o);
                 if (op.code == OP_UPDATE) {
                     do_update<double, BS, KP, kPmGlobal>(vd, op, 0, ni);
                 } else {
