@@ -1658,9 +1658,9 @@ __global__ void __launch_bounds__(BS) k_optimize(const BatchArgs a, double *brle
         // FP64 partials: the matrices, then the lengths, in LDS.  FP32
         // partials: the lengths, then (16-byte aligned) an FP32 copy of the
         // matrices for the loop's updates in LDS, while the FP64 matrices,
-        // read only by the final FP64 evaluation, go to this tree's slice of
-        // the global matrix buffer (so a 64-taxon tree's table still fits
-        // in LDS beside them).
+        // read only by the final FP64 evaluation, are written once before it
+        // to this tree's slice of the global matrix buffer (so a 64-taxon
+        // tree's table still fits in LDS beside the FP32 copy).
         constexpr bool kF32 = std::is_same<T, float>::value;
         constexpr bool kFuseUpd = GRP && TAB_LDS && FuseFirst<KP>::value && BS == 256;
         double *pm = kF32 ? a.pmat + td.pm_off : lds;
@@ -1682,8 +1682,8 @@ __global__ void __launch_bounds__(BS) k_optimize(const BatchArgs a, double *brle
         for (int x = tid; x < E * KP * 16; x += BS) {
             const int e = x / (KP * 16), r = x % (KP * 16);
             const double pe = pm_entry(&model, r >> 4, r & 15, tl[e]);
-            pm[x] = pe;
             if (kF32) pmf[x] = (float)pe;
+            else pm[x] = pe;
         }
         __syncthreads();
         TreeView<T> v = make_view<T>(td, aln, a, &model, pm);
@@ -1793,14 +1793,14 @@ __global__ void __launch_bounds__(BS) k_optimize(const BatchArgs a, double *brle
                         __builtin_amdgcn_wave_barrier();
                         if (tid < KP * 16) {
                             const double pe = pm_entry_ex(&model, pm_ex, tid >> 4, tid & 15);
-                            pm[(size_t)e * KP * 16 + tid] = pe;
                             if (kF32) pmf[(size_t)e * KP * 16 + tid] = (float)pe;
+                            else pm[(size_t)e * KP * 16 + tid] = pe;
                         }
                     } else {
                         if (tid < KP * 16) {
                             const double pe = pm_entry(&model, tid >> 4, tid & 15, r.t);
-                            pm[(size_t)e * KP * 16 + tid] = pe;
                             if (kF32) pmf[(size_t)e * KP * 16 + tid] = (float)pe;
+                            else pm[(size_t)e * KP * 16 + tid] = pe;
                         }
                     }
                     __syncthreads();
@@ -1815,6 +1815,17 @@ __global__ void __launch_bounds__(BS) k_optimize(const BatchArgs a, double *brle
             }
             if (passes >= opt.max_passes) break;
             prev = cur;
+        }
+        if (kF32 && td.n_final > 0) {
+            // The FP64 matrices at the final lengths, for the FP64 pass below
+            // (the loop's updates read only the FP32 copy in LDS, so no FP64
+            // matrix is stored during the loop).  Every block of a tree
+            // computes the same values from the same lengths.
+            for (int x = tid; x < E * KP * 16; x += BS) {
+                const int e = x / (KP * 16), r = x % (KP * 16);
+                pm[x] = pm_entry(&model, r >> 4, r & 15, tl[e]);
+            }
+            if (!GRP) __syncthreads();
         }
         if (GRP && kF32 && td.n_final > 0) {
             // The FP64 pass below reuses the tree's buffer in another layout,
