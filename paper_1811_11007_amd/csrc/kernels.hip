@@ -666,10 +666,11 @@ __device__ inline void table_coeffs(const ModelS *md, const SA &sa, const SB &sb
 }
 
 // This thread's contributions to lnL, d1 and d2 across an edge whose sides
-// are of kinds TA / TB, with the exponentials of its length in wx.
+// are of kinds TA / TB, with the exponentials of its length in wx (lnL only
+// with want_l0: a gradient program reads it from one edge's output only).
 template <typename T, int BS, int KP, bool TA, bool TB>
 __device__ inline void eval_sides(const TreeView<T> &v, int a, int b, int base, int ni, const double *wx,
-                                  double logK, Sums3 &r) {
+                                  double logK, bool want_l0, Sums3 &r) {
     const ModelS *md = v.m;
 #pragma unroll 1
     for (int j = 0; j < ni; ++j) {
@@ -698,27 +699,28 @@ __device__ inline void eval_sides(const TreeView<T> &v, int a, int b, int base, 
         }
         const double inv = recip(L);
         const double r1 = L1 * inv;
-        r.l0 += w * (log(L) + const_term<T>(sa.c + sb.c, logK));
+        if (want_l0) r.l0 += w * (log(L) + const_term<T>(sa.c + sb.c, logK));
         r.l1 += w * r1;
         r.l2 += w * (L2 * inv - r1 * r1);
     }
 }
 
-// OP_EVAL: block totals of lnL and its first two derivatives across an edge
-// at length t, computed on the fly from the two sides.
+// OP_EVAL: block totals of lnL (0 unless want_l0) and its first two
+// derivatives across an edge at length t, computed on the fly from the two
+// sides.
 template <typename T, int BS, int KP>
 __device__ inline Sums3 eval_edge(const TreeView<T> &v, int a, int b, int base, int ni, double t, double *red,
-                                  double *wx, int parity, GroupS *gs = nullptr) {
+                                  double *wx, int parity, GroupS *gs = nullptr, bool want_l0 = true) {
     wave_expo(wx, v.m, v.K, t);
     const double logK = log((double)v.K);
     Sums3 r;
     r.l0 = r.l1 = r.l2 = 0.0;
     if (a < 0) {
-        if (b < 0) eval_sides<T, BS, KP, true, true>(v, a, b, base, ni, wx, logK, r);
-        else eval_sides<T, BS, KP, true, false>(v, a, b, base, ni, wx, logK, r);
+        if (b < 0) eval_sides<T, BS, KP, true, true>(v, a, b, base, ni, wx, logK, want_l0, r);
+        else eval_sides<T, BS, KP, true, false>(v, a, b, base, ni, wx, logK, want_l0, r);
     } else {
-        if (b < 0) eval_sides<T, BS, KP, false, true>(v, a, b, base, ni, wx, logK, r);
-        else eval_sides<T, BS, KP, false, false>(v, a, b, base, ni, wx, logK, r);
+        if (b < 0) eval_sides<T, BS, KP, false, true>(v, a, b, base, ni, wx, logK, want_l0, r);
+        else eval_sides<T, BS, KP, false, false>(v, a, b, base, ni, wx, logK, want_l0, r);
     }
     group_sum3<BS>(r.l0, r.l1, r.l2, red, parity, gs);
     r.parity = parity;
@@ -1324,8 +1326,10 @@ __device__ inline void tiles_body(const BatchArgs &a, const double *brlen) {
             last_dst = op.dst;
             continue;
         }
-        const Sums3 r =
-            eval_edge<T, BS, KP>(v, op.a, op.b, base, kTileItems, brlen[td.edge_off + op.dst], red, wx, parity);
+        // lnL is read from output column 0 only (the likelihood program's one
+        // edge, the gradient program's first edge)
+        const Sums3 r = eval_edge<T, BS, KP>(v, op.a, op.b, base, kTileItems, brlen[td.edge_off + op.dst], red, wx,
+                                             parity, nullptr, op.ea == 0);
         parity = r.parity;
         if (threadIdx.x == 0) {
             double *out = a.part + ((size_t)tile * a.part_cols + op.ea) * 3;
