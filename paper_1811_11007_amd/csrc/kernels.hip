@@ -1192,24 +1192,41 @@ __global__ void k_fill_i32(int32_t *p, int32_t v, int64_t n) {
     if (i < n) p[i] = v;
 }
 
-// Transition matrices of every flat edge: one thread per edge.
+// Transition matrices of every flat edge, P_k(t) = U diag(exp(lambda r_k t))
+// U^-1: one thread per (edge, category k).  The model constants are read once
+// into registers before the first store (stores through the output pointer
+// could otherwise alias them and force reloads), and the four exponentials
+// serve the matrix's 16 entries, written as 16-byte stores.
 __global__ void k_pmat(const BatchArgs a, const double *brlen) {
-    const int64_t fe = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t fe = g / a.kp;
     if (fe >= a.n_edges) return;
+    const int k = (int)(g - fe * a.kp);
     const TreeDev &td = a.trees[a.edge_tree[fe]];
     const AlnDev *aln = a.alns + td.aln;
-    const int Kp = a.kp;
     const double t = brlen[fe];
-    double *out = a.pmat + td.pm_off + (fe - td.edge_off) * Kp * 16;
-    for (int k = 0; k < Kp; ++k) {
-        double e[4];
-        for (int m = 0; m < 4; ++m) e[m] = exp(aln->lam[m] * aln->rate[k] * t);
-        for (int ij = 0; ij < 16; ++ij) {
-            const int i = ij >> 2, j = ij & 3;
+    double U[16], V[16], e[4];
+#pragma unroll
+    for (int x = 0; x < 16; ++x) {
+        U[x] = aln->U[x];
+        V[x] = aln->Uinv[x];
+    }
+    const double rk = aln->rate[k];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) e[m] = exp(aln->lam[m] * rk * t);
+    double2 *out = reinterpret_cast<double2 *>(a.pmat + td.pm_off + ((fe - td.edge_off) * a.kp + k) * 16);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        double s2[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int i = (2 * q + h) >> 2, j = (2 * q + h) & 3;
             double s = 0.0;
-            for (int m = 0; m < 4; ++m) s += aln->U[i * 4 + m] * e[m] * aln->Uinv[m * 4 + j];
-            out[k * 16 + ij] = s;
+#pragma unroll
+            for (int m = 0; m < 4; ++m) s += U[i * 4 + m] * e[m] * V[m * 4 + j];
+            s2[h] = s;
         }
+        out[q] = make_double2(s2[0], s2[1]);
     }
 }
 
@@ -1252,6 +1269,23 @@ __device__ inline void update_keep(const TreeView<T> &v, const Op &op, int p, Si
     v.cnt[(size_t)op.dst * v.P + p] = (uint16_t)last.c;
 }
 
+// Requests one update's transition matrices (edges ea and eb, KP categories
+// each) into the L2 ahead of use: one 16-byte LDS DMA per lane of the calling
+// wave into `row`, which nobody reads.  The FP32 tile kernel reads the
+// matrices by scalar loads, which its register budget serialises in pairs
+// per update; issued one op early, these requests let those loads find the
+// lines in the L2 instead of going out to memory one pair after another.
+template <int KP>
+__device__ inline void prefetch_pm(const double *pm, int ea, int eb, float4 *row) {
+    constexpr int kChunks = KP * 8;  // 16-byte pieces of one edge's KP matrices
+    const int lane = threadIdx.x & 63;
+    if (lane < 2 * kChunks) {
+        const double *src = pm + ((size_t)(lane < kChunks ? ea : eb) * KP) * 16 + (lane % kChunks) * 2;
+        __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)src,
+                                         (__attribute__((address_space(3))) void *)row, 16, 0, 0);
+    }
+}
+
 // Pattern-tile kernels (k_tiles32 / k_tiles64 below): each block runs its tree's program over one tile of
 // BS * kTileItems patterns.  LOGLIK programs end in one EVAL (column 0);
 // GRAD programs EVAL every edge.  Output: part[tile][col] = (lnL, d1, d2).
@@ -1261,6 +1295,7 @@ __device__ inline void tiles_body(const BatchArgs &a, const double *brlen) {
     __shared__ double red[2 * (BS / 64) * 3];
     __shared__ double wxs[(BS / 64) * kWx];
     __shared__ ModelS model;
+    __shared__ float4 pf_row[64];  // target of prefetch_pm, never read
     // FP32 partials: the updates read the tree's transition matrices (written
     // by k_pmat before this launch) in place by scalar loads (see PmPtr);
     // FP64 partials: from a copy in LDS, which measured faster there.
@@ -1301,8 +1336,22 @@ __device__ inline void tiles_body(const BatchArgs &a, const double *brlen) {
     const bool live_p = p < v.np;
     Side<T, KP, false> last;
     int last_dst = -1;
+    // FP32 partials: the first wave requests each update's matrices into the
+    // L2 one op ahead of the update
+    if constexpr (kConstPm) {
+        if (threadIdx.x < 64 && td.n_first > 0) {
+            const Op nx = load_op(a.ops, td.op_first);
+            if (nx.code == OP_UPDATE) prefetch_pm<KP>(a.pmat + td.pm_off, nx.ea, nx.eb, pf_row);
+        }
+    }
     for (int o = 0; o < td.n_first; ++o) {
         const Op op = load_op(a.ops, td.op_first + o);
+        if constexpr (kConstPm) {
+            if (threadIdx.x < 64 && o + 1 < td.n_first) {
+                const Op nx = load_op(a.ops, td.op_first + o + 1);
+                if (nx.code == OP_UPDATE) prefetch_pm<KP>(a.pmat + td.pm_off, nx.ea, nx.eb, pf_row);
+            }
+        }
         if (op.code == OP_UPDATE && !kForward) {
             do_update<T, BS, KP, PMK>(v, op, base, kTileItems);
             continue;
@@ -1996,7 +2045,8 @@ hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s) {
 
 hipError_t launch_pmat(const BatchArgs &a, const double *brlen, hipStream_t s) {
     if (a.n_edges <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_pmat, dim3((unsigned)((a.n_edges + 127) / 128)), dim3(128), 0, s, a, brlen);
+    const int64_t n = a.n_edges * (int64_t)a.kp;
+    hipLaunchKernelGGL(k_pmat, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a, brlen);
     return hipGetLastError();
 }
 
