@@ -1463,17 +1463,22 @@ __device__ inline void reg_copy(double d[4], const double s[4]) {
     d[0] = s[0]; d[1] = s[1]; d[2] = s[2]; d[3] = s[3];
 }
 
-// The stack lives in LDS, [slot][item][thread] of four doubles (a stack
-// indexed by a runtime slot number does not stay in registers); the
-// accumulators, which most steps read and write, are in registers.
-template <int KP>
+// The accumulators, which most steps read and write, are in registers.  The
+// stack: with RSLOTS > 0 (programs needing at most RSLOTS slots) in
+// registers too, each slot selected by its wave-uniform number against
+// compile-time indices (an array indexed by a runtime number would go to
+// scratch memory), which leaves LDS to the tip codes alone and lets more
+// blocks share a compute unit; with RSLOTS = 0 in LDS, [slot][item][thread]
+// of four doubles.
+template <int KP, int RSLOTS>
 __global__ void __launch_bounds__(RegShape<KP>::kThreads) k_loglik_reg(const BatchArgs a) {
     using RS = RegShape<KP>;
     constexpr int NI = RS::kItems;
-    // dynamic LDS: the stack [kRegStack or fewer][kItems][kThreads] of
-    // double4, then the tile's tip codes [n][kPats]
+    // dynamic LDS: with RSLOTS = 0 the stack [reg_depth][kItems][kThreads] of
+    // double4; then the tile's tip codes [n][kPats]
     extern __shared__ double4 stack_lds[];
-    uint8_t *tip_lds = reinterpret_cast<uint8_t *>(stack_lds + (size_t)a.reg_depth * NI * RS::kThreads);
+    const int lds_slots = RSLOTS > 0 ? 0 : a.reg_depth;
+    uint8_t *tip_lds = reinterpret_cast<uint8_t *>(stack_lds + (size_t)lds_slots * NI * RS::kThreads);
     __shared__ double cat_l[RS::kWaves][RS::kGroupPats];
     __shared__ int cat_c[RS::kWaves][RS::kGroupPats];
     __shared__ double grp_sum[RS::kGroups];
@@ -1513,6 +1518,7 @@ __global__ void __launch_bounds__(RegShape<KP>::kThreads) k_loglik_reg(const Bat
         L[j] = 0.0;
     }
     double4 *stk = stack_lds + threadIdx.x;  // item j, slot s at stk[(s * NI + j) * kThreads]
+    double4 rstk[RSLOTS > 0 ? RSLOTS : 1][NI];  // slot s, item j (RSLOTS > 0)
     // One step for item j.  The compiler emits three side forms (see
     // compile_loglik_reg): two tips; the accumulator and a tip; a stack slot
     // and the accumulator.  Each form has its own straight-line code so that
@@ -1547,7 +1553,16 @@ __global__ void __launch_bounds__(RegShape<KP>::kThreads) k_loglik_reg(const Bat
         if (op.code == OP_RPUSH) {
 #pragma unroll
             for (int j = 0; j < NI; ++j)
-                stk[((size_t)op.dst * NI + j) * RS::kThreads] = make_double4(acc[j][0], acc[j][1], acc[j][2], acc[j][3]);
+            {
+                const double4 x = make_double4(acc[j][0], acc[j][1], acc[j][2], acc[j][3]);
+                if constexpr (RSLOTS > 0) {
+#pragma unroll
+                    for (int q = 0; q < RSLOTS; ++q)
+                        if (q == op.dst) rstk[q][j] = x;
+                } else {
+                    stk[((size_t)op.dst * NI + j) * RS::kThreads] = x;
+                }
+            }
             continue;
         }
         // both matrices are used on every path, so their loads issue together
@@ -1593,7 +1608,17 @@ __global__ void __launch_bounds__(RegShape<KP>::kThreads) k_loglik_reg(const Bat
         } else {  // a stack slot and the accumulator
             double4 v[NI];
 #pragma unroll
-            for (int j = 0; j < NI; ++j) v[j] = stk[((size_t)(REF_STACK0 - op.a) * NI + j) * RS::kThreads];
+            for (int j = 0; j < NI; ++j) {
+                const int slot = REF_STACK0 - op.a;
+                if constexpr (RSLOTS > 0) {
+                    v[j] = rstk[0][j];
+#pragma unroll
+                    for (int q = 1; q < RSLOTS; ++q)
+                        if (q == slot) v[j] = rstk[q][j];
+                } else {
+                    v[j] = stk[((size_t)slot * NI + j) * RS::kThreads];
+                }
+            }
 #pragma unroll
             for (int x = 0; x < 16; ++x) {
                 ma[x] = Pa[x];
@@ -2071,22 +2096,30 @@ int loglik_reg_tile_patterns(int kp) {
 }
 
 size_t loglik_reg_lds(int kp, int n, int depth) {
-    PT_KP_SWITCH(return (size_t)depth * RegShape<KP>::kItems * RegShape<KP>::kThreads * sizeof(double4) +
+    // programs of at most kRegStackRegs slots keep their stack in registers
+    const int lds_slots = depth <= kRegStackRegs ? 0 : depth;
+    PT_KP_SWITCH(return (size_t)lds_slots * RegShape<KP>::kItems * RegShape<KP>::kThreads * sizeof(double4) +
                         (size_t)n * RegShape<KP>::kPats);
     return 0;
 }
 
 hipError_t launch_loglik_reg(int kp, const BatchArgs &a, size_t lds_bytes, hipStream_t s) {
     if (a.n_tiles <= 0) return hipSuccess;
+#define PT_REG_LAUNCH(RSL)                                                                                  \
+    do {                                                                                                    \
+        if (lds_bytes > 48 * 1024) {                                                                        \
+            hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_loglik_reg<KP, RSL>),       \
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes); \
+            if (e != hipSuccess) return e;                                                                  \
+        }                                                                                                   \
+        hipLaunchKernelGGL((k_loglik_reg<KP, RSL>), dim3(a.n_tiles), dim3(RegShape<KP>::kThreads), lds_bytes, s, a); \
+        return hipGetLastError();                                                                           \
+    } while (0)
     PT_KP_SWITCH({
-        if (lds_bytes > 48 * 1024) {
-            hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_loglik_reg<KP>),
-                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
-            if (e != hipSuccess) return e;
-        }
-        hipLaunchKernelGGL((k_loglik_reg<KP>), dim3(a.n_tiles), dim3(RegShape<KP>::kThreads), lds_bytes, s, a);
-        return hipGetLastError();
+        if (a.reg_depth <= kRegStackRegs) PT_REG_LAUNCH(kRegStackRegs);
+        PT_REG_LAUNCH(0);
     });
+#undef PT_REG_LAUNCH
     return hipErrorInvalidValue;
 }
 

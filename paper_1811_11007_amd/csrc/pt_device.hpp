@@ -32,7 +32,8 @@ enum : int32_t {
 // accumulator, or stack slot REF_STACK0 - ref.
 constexpr int32_t REF_ACC = -1;
 constexpr int32_t REF_STACK0 = -2;
-constexpr int kRegStack = 8;  // stack slots of the register kernel
+constexpr int kRegStack = 8;      // stack slots of the register kernel
+constexpr int kRegStackRegs = 4;  // programs of at most this many slots keep the stack in registers
 
 struct Op {
     int32_t code;

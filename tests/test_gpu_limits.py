@@ -135,3 +135,43 @@ def test_lds_limit(ctx):
         return
     say("150 taxa x 8 categories lnL", got, "oracle", want)
     assert abs(got - want) <= 1e-11 * abs(want)
+
+
+def balanced_tree(n_leaves, rng, mean=0.1):
+    """Perfectly balanced unrooted tree on a power of two leaves: pairs joined
+    level by level, the two halves joined by edge 0.  The likelihood's
+    register program is rooted on edge 0, so it needs log2(n) - 1 stack
+    slots, the most any tree of n taxa needs."""
+    nodes, nxt, edges = list(range(n_leaves)), n_leaves, []
+    while len(nodes) > 2:
+        up = []
+        for i in range(0, len(nodes), 2):
+            edges += [(nodes[i], nxt), (nodes[i + 1], nxt)]
+            up.append(nxt)
+            nxt += 1
+        nodes = up
+    e = np.array([(nodes[0], nodes[1])] + edges, np.int32)
+    return e, rng.exponential(mean, size=len(e))
+
+
+def test_register_stack_depths(ctx):
+    """The register-resident lnL keeps a program's stack in registers up to
+    four slots and in LDS beyond: balanced trees of 32 taxa (four slots) and
+    64 taxa (five), and Yule trees, against the oracle in one batch."""
+    rng = np.random.default_rng(95)
+    for n in (32, 64):
+        e, b = balanced_tree(n, rng)
+        ey, by = synth.yule_tree(n, rng, mean=0.1)
+        aln = synth.make_alignment(e, b, n, 400, rng, alpha=0.5, n_cats=4)
+        D = oc.Data.from_alignment(aln)
+        A = pt.Alignment.from_synth(ctx, aln)
+        want = np.array([oc.loglik(D, e, b), oc.loglik(D, ey, by)])
+        T = pt.Trees([e, ey])
+        for batch in ([0, 1], [0], [1]):
+            Tb = pt.Trees([[e, ey][i] for i in batch])
+            lens = np.concatenate([[b, by][i] for i in batch])
+            for prec in (pt.PT_FP64, pt.PT_FP32):
+                got = pt.pt_batch_loglik(ctx, [A], Tb, lens, precision=prec)
+                say("balanced/yule", n, "batch", batch, "prec", prec, "rel", np.abs(got - want[batch]) / np.abs(want[batch]))
+                assert np.all(np.abs(got - want[batch]) <= 1e-11 * np.abs(want[batch]))
+        del T
