@@ -1469,9 +1469,11 @@ __device__ inline void reg_copy(double d[4], const double s[4]) {
 // compile-time indices (an array indexed by a runtime number would go to
 // scratch memory), which leaves LDS to the tip codes alone and lets more
 // blocks share a compute unit; with RSLOTS = 0 in LDS, [slot][item][thread]
-// of four doubles.
+// of four doubles.  Three register slots fit five waves per SIMD, four slots
+// four.
 template <int KP, int RSLOTS>
-__global__ void __launch_bounds__(RegShape<KP>::kThreads) k_loglik_reg(const BatchArgs a) {
+__global__ void __launch_bounds__(RegShape<KP>::kThreads) __attribute__((amdgpu_waves_per_eu(RSLOTS == 3 ? 5 : 4)))
+k_loglik_reg(const BatchArgs a) {
     using RS = RegShape<KP>;
     constexpr int NI = RS::kItems;
     // dynamic LDS: with RSLOTS = 0 the stack [reg_depth][kItems][kThreads] of
@@ -2116,7 +2118,9 @@ hipError_t launch_loglik_reg(int kp, const BatchArgs &a, size_t lds_bytes, hipSt
         return hipGetLastError();                                                                           \
     } while (0)
     PT_KP_SWITCH({
-        if (a.reg_depth <= kRegStackRegs) PT_REG_LAUNCH(kRegStackRegs);
+        static_assert(kRegStackRegs == 4, "register stacks of three and four slots");
+        if (a.reg_depth <= 3) PT_REG_LAUNCH(3);
+        if (a.reg_depth <= 4) PT_REG_LAUNCH(4);
         PT_REG_LAUNCH(0);
     });
 #undef PT_REG_LAUNCH
