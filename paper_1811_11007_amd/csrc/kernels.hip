@@ -1192,41 +1192,40 @@ __global__ void k_fill_i32(int32_t *p, int32_t v, int64_t n) {
     if (i < n) p[i] = v;
 }
 
-// Transition matrices of every flat edge, P_k(t) = U diag(exp(lambda r_k t))
-// U^-1: one thread per (edge, category k).  The model constants are read once
-// into registers before the first store (stores through the output pointer
-// could otherwise alias them and force reloads), and the four exponentials
+// Transition matrices of every edge, P_k(t) = U diag(exp(lambda r_k t)) U^-1:
+// one block per tree, so that the tree's descriptor and model constants are
+// wave-uniform and arrive by scalar loads (neither is written by any kernel),
+// and one thread per (edge, category k) of the tree.  The four exponentials
 // serve the matrix's 16 entries, written as 16-byte stores.
 __global__ void k_pmat(const BatchArgs a, const double *brlen) {
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t fe = g / a.kp;
-    if (fe >= a.n_edges) return;
-    const int k = (int)(g - fe * a.kp);
-    const TreeDev &td = a.trees[a.edge_tree[fe]];
-    const AlnDev *aln = a.alns + td.aln;
-    const double t = brlen[fe];
-    double U[16], V[16], e[4];
+    using CD = const __attribute__((address_space(4))) double;
+    const __attribute__((address_space(4))) TreeDev *td =
+        (const __attribute__((address_space(4))) TreeDev *)(a.trees + blockIdx.x);
+    const __attribute__((address_space(4))) AlnDev *aln =
+        (const __attribute__((address_space(4))) AlnDev *)(a.alns + td->aln);
+    const int kp = a.kp, n = td->n_edges * kp;
+    const int64_t edge_off = td->edge_off, pm_off = td->pm_off;
+    for (int x = threadIdx.x; x < n; x += blockDim.x) {
+        const int e = x / kp, k = x - e * kp;
+        const double t = brlen[edge_off + e];
+        CD *U = aln->U, *V = aln->Uinv;
+        double ex[4];
 #pragma unroll
-    for (int x = 0; x < 16; ++x) {
-        U[x] = aln->U[x];
-        V[x] = aln->Uinv[x];
-    }
-    const double rk = aln->rate[k];
+        for (int m = 0; m < 4; ++m) ex[m] = exp(aln->lam[m] * aln->rate[k] * t);
+        double2 *out = reinterpret_cast<double2 *>(a.pmat + pm_off + (int64_t)x * 16);
 #pragma unroll
-    for (int m = 0; m < 4; ++m) e[m] = exp(aln->lam[m] * rk * t);
-    double2 *out = reinterpret_cast<double2 *>(a.pmat + td.pm_off + ((fe - td.edge_off) * a.kp + k) * 16);
+        for (int q = 0; q < 8; ++q) {
+            double s2[2];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-        double s2[2];
+            for (int h = 0; h < 2; ++h) {
+                const int i = (2 * q + h) >> 2, j = (2 * q + h) & 3;
+                double s = 0.0;
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int i = (2 * q + h) >> 2, j = (2 * q + h) & 3;
-            double s = 0.0;
-#pragma unroll
-            for (int m = 0; m < 4; ++m) s += U[i * 4 + m] * e[m] * V[m * 4 + j];
-            s2[h] = s;
+                for (int m = 0; m < 4; ++m) s += U[i * 4 + m] * ex[m] * V[m * 4 + j];
+                s2[h] = s;
+            }
+            out[q] = make_double2(s2[0], s2[1]);
         }
-        out[q] = make_double2(s2[0], s2[1]);
     }
 }
 
@@ -2072,8 +2071,7 @@ hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s) {
 
 hipError_t launch_pmat(const BatchArgs &a, const double *brlen, hipStream_t s) {
     if (a.n_edges <= 0) return hipSuccess;
-    const int64_t n = a.n_edges * (int64_t)a.kp;
-    hipLaunchKernelGGL(k_pmat, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a, brlen);
+    hipLaunchKernelGGL(k_pmat, dim3((unsigned)a.n_trees), dim3(256), 0, s, a, brlen);
     return hipGetLastError();
 }
 
