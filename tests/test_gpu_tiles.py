@@ -123,3 +123,55 @@ def test_gradient_at_every_tile_size_and_autotuned(ctx):
         again = pt.Plan(ctx, [A], T, pt.PT_PLAN_GRAD, prec)
         assert again.tile_patterns() == best
         again.close()
+
+
+def test_few_categories_at_every_tile_size(ctx):
+    """The stored pass and the gradient with one and two rate categories
+    (their own tile kernel instantiations, each requesting its update's
+    matrices ahead: 8 and 16 lanes of 16 bytes per edge), at 64, 128 and 256
+    patterns per tile with ragged last tiles, in both precisions, against
+    the oracle."""
+    import synth
+    from oracle import core as oc
+    rng = np.random.default_rng(97)
+    dev = torch.device("cuda:0")
+    for K in (1, 2):
+        for n, sites in ((12, 700), (30, 450)):
+            e0, b0 = synth.yule_tree(n, rng, mean=0.08)
+            aln = synth.make_alignment(e0, b0, n, sites, rng, alpha=0.7, n_cats=K)
+            D = oc.Data.from_alignment(aln)
+            A = pt.Alignment.from_synth(ctx, aln)
+            tops = [e0] + [synth.yule_tree(n, rng, mean=0.08)[0] for _ in range(3)]
+            lens = [b0 * rng.uniform(0.6, 1.4, size=len(b0)) for _ in tops]
+            want = [oc.gradient(D, t, l) for t, l in zip(tops, lens)]
+            wl = np.array([w[0] for w in want])
+            wg = np.concatenate([w[1] for w in want])
+            T = pt.Trees(tops)
+            b = torch.tensor(np.concatenate(lens), dtype=torch.float64, device=dev)
+            for prec in (pt.PT_FP64, pt.PT_FP32):
+                pl = pt.Plan(ctx, [A], T, pt.PT_PLAN_LOGLIK, prec)
+                pl.set_loglik_path(pt.PT_LOGLIK_STORED)
+                pg = pt.Plan(ctx, [A], T, pt.PT_PLAN_GRAD, prec)
+                for pats in (64, 128, 256):
+                    pl.set_tile_patterns(pats)
+                    pg.set_tile_patterns(pats)
+                    l = torch.zeros(T.n_trees, dtype=torch.float64, device=dev)
+                    pl.loglik(b, l)
+                    lg = torch.zeros(T.n_trees, dtype=torch.float64, device=dev)
+                    gg = torch.zeros_like(b)
+                    pg.grad(b, lg, gg)
+                    torch.cuda.synchronize()
+                    got, gl, gr = l.cpu().numpy(), lg.cpu().numpy(), gg.cpu().numpy()
+                    eg = np.max(np.abs(gr - wg) / np.maximum(1.0, np.abs(wg)))
+                    say("K", K, "n", n, "prec", prec, "tile", pats, "lnL", np.max(np.abs(got - wl)),
+                        "grad lnL", np.max(np.abs(gl - wl)), "grad", eg)
+                    if prec == pt.PT_FP64:
+                        assert np.max(np.abs(got - wl) / np.abs(wl)) < FP64_REL
+                        assert np.max(np.abs(gl - wl) / np.abs(wl)) < FP64_REL
+                        assert eg < 1e-7
+                    else:
+                        assert np.max(np.abs(got - wl)) < FP32_ABS
+                        assert np.max(np.abs(gl - wl)) < FP32_ABS
+                        assert eg < 1e-3
+                pl.close()
+                pg.close()
